@@ -1,0 +1,331 @@
+/*
+ * Test oracle for the separable bispectrum projection Gamma.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load or call this library.  The
+ * product (the HIP library under paper_1503_08809_amd/) never links it and
+ * shares no code with it.
+ *
+ * Plain, slow, obviously-correct FP64 C (OpenMP over independent outer
+ * indices only).  Each function cites the passage of the paper it follows:
+ *
+ *   Sec. 2.2, Eq. (2D)        Gamma'_nn' = 1/(48 pi) Int r^2 dr Int dmu (P_ii' P_jj' P_kk' + 5 perms)
+ *   Sec. 2.2, Eq. (legendre)  P_ii'(r,mu) = Sum_l (2l+1)/(v_l sqrt(C_l)) qt_i'(r,l) q_i(l) P_l(mu)
+ *   Appendix, projection      qt_i(r,l) = Int dk k^2 qbar_i(k) Delta_l(k) j_l(k r)
+ *   Appendix, S/N weighting   v_l = (2l+1)^(1/6)
+ *   Sec. 2.2                  Gauss-Legendre quadrature of the polynomial mu-integrand;
+ *                             the mu integral is done before the r integral
+ *   Sec. 3.2.3                trapezium rule for the r integral (weights are inputs here)
+ *
+ * Names in this file: S_ap(r,mu) is the paper's P_ii'(r,mu) with a <-> i
+ * (late-time mode) and p <-> i' (primordial mode); beta_p(l,r) is the
+ * paper's projected mode qt_p(r,l), carrying an extra 2/pi.
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *   - beta carries the factor 2/pi of the spherical-Bessel projection.
+ *   - The per-l weight is w_l = (2l+1)^(1 - v_power) / sqrt(C_l)
+ *     (v_power = 1/6 reproduces (2l+1)/(v_l sqrt(C_l))).
+ *   - The "ordered" projection drops the symmetrisation:
+ *     Gamma_ord = 1/(8 pi) Int r^2 Int dmu S_a1p1 S_a2p2 S_a3p3.
+ *   - The symmetric projection keeps all six permutation terms with
+ *     multiplicity (the permanent of the 3x3 block S_{a_s p_t}).
+ *   - j_l(x) below l_s(x) = ceil(x + 20 x^(1/3) + 50) only; above it the
+ *     function is smaller than 1e-20 of its peak and is returned as 0.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_PI 3.14159265358979323846264338327950288
+
+/* ------------------------------------------------------------------ */
+/* Gauss-Legendre nodes and weights (Sec. 2.2): Newton iteration on    */
+/* P_n(x) evaluated by the three-term recurrence, in long double.      */
+/* Nodes ascending; weights w = 2 / ((1 - x^2) P_n'(x)^2).             */
+/* ------------------------------------------------------------------ */
+static void or_pn_and_deriv(int n, long double x, long double *pn, long double *dpn)
+{
+    long double p0 = 1.0L, p1 = x;
+    if (n == 0) { *pn = 1.0L; *dpn = 0.0L; return; }
+    for (int l = 1; l < n; ++l) {
+        long double p2 = ((2.0L * l + 1.0L) * x * p1 - (long double)l * p0) / (long double)(l + 1);
+        p0 = p1;
+        p1 = p2;
+    }
+    *pn = p1;
+    *dpn = (long double)n * (x * p1 - p0) / (x * x - 1.0L);
+}
+
+int or_gauss_legendre(int n, double *x, double *w)
+{
+    if (n <= 0 || !x || !w) return -1;
+    int half = (n + 1) / 2;
+    for (int i = 0; i < half; ++i) {
+        /* i-th largest root: initial guess cos(pi (i + 3/4) / (n + 1/2)) */
+        long double z = cosl((long double)OR_PI * ((long double)i + 0.75L) / ((long double)n + 0.5L));
+        long double pn = 0, dpn = 0;
+        for (int it = 0; it < 100; ++it) {
+            or_pn_and_deriv(n, z, &pn, &dpn);
+            long double dz = pn / dpn;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        or_pn_and_deriv(n, z, &pn, &dpn);
+        long double wi = 2.0L / ((1.0L - z * z) * dpn * dpn);
+        /* root i (descending) sits at ascending index n-1-i; mirror to i */
+        x[n - 1 - i] = (double)z;
+        w[n - 1 - i] = (double)wi;
+        x[i] = -(double)z;
+        w[i] = (double)wi;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Legendre table P[j][l] = P_l(mu_j), l = 0..lmax (Sec. 2.2: the      */
+/* mu-integrand of Eq. (legendre)).  Bonnet recurrence                 */
+/* (l+1) P_{l+1} = (2l+1) mu P_l - l P_{l-1}.                          */
+/* ------------------------------------------------------------------ */
+void or_legendre_table(int lmax, int nmu, const double *mu, double *P)
+{
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < nmu; ++j) {
+        double *row = P + (size_t)j * (lmax + 1);
+        double x = mu[j];
+        row[0] = 1.0;
+        if (lmax >= 1) row[1] = x;
+        for (int l = 1; l < lmax; ++l)
+            row[l + 1] = ((2.0 * l + 1.0) * x * row[l] - (double)l * row[l - 1]) / (double)(l + 1);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Spherical Bessel j_l(x), l = 0..lmax (Appendix: the kernel of the   */
+/* projection qt_i(r,l)).  Upward recurrence                           */
+/* j_{l+1} = (2l+1)/x j_l - j_{l-1} from the closed forms j_0, j_1 for */
+/* l <= floor(x) (the oscillatory region, where upward is stable); a   */
+/* Miller downward recurrence for l > floor(x), scaled to the upward   */
+/* values at floor(x) and floor(x)-1 by least squares.                 */
+/* ------------------------------------------------------------------ */
+static double or_j1_closed(double x)
+{
+    if (x < 0.05) {
+        double x2 = x * x;   /* series x/3 (1 - x^2/10 + x^4/280 - x^6/15120) */
+        return x / 3.0 * (1.0 - x2 / 10.0 * (1.0 - x2 / 28.0 * (1.0 - x2 / 54.0)));
+    }
+    return sin(x) / (x * x) - cos(x) / x;
+}
+
+static void or_sph_bessel_one(int lmax, double x, double *j, double *work)
+{
+    for (int l = 0; l <= lmax; ++l) j[l] = 0.0;
+    if (x == 0.0) { j[0] = 1.0; return; }
+    double j0 = (x < 1e-4) ? 1.0 - x * x / 6.0 : sin(x) / x;
+    double j1 = or_j1_closed(x);
+    double fx = floor(x);
+    int nup = (fx >= (double)lmax) ? lmax : (int)fx;
+    /* upward part, l <= nup */
+    j[0] = j0;
+    if (lmax >= 1) j[1] = j1;
+    for (int l = 1; l < nup; ++l) j[l + 1] = (2.0 * l + 1.0) / x * j[l] - j[l - 1];
+    if (nup >= lmax) return;
+    /* downward (Miller) part, l > nup */
+    int ls = (int)ceil(x + 20.0 * cbrt(x) + 50.0);
+    int top = ls;
+    int m = nup >= 1 ? nup : 1;          /* match at m and m-1 */
+    if (top < m + 1) top = m + 1;
+    double *f = work;                    /* f[0..top+1] */
+    f[top + 1] = 0.0;
+    f[top] = 1e-280;
+    for (int l = top; l >= 1; --l) {
+        f[l - 1] = (2.0 * l + 1.0) / x * f[l] - f[l + 1];
+        if (fabs(f[l - 1]) > 1e250) {
+            for (int q = l - 1; q <= top; ++q) f[q] *= 1e-250;
+        }
+    }
+    double um = (m == 1) ? j1 : j[m];
+    double um1 = (m - 1 == 0) ? j0 : j[m - 1];
+    /* least-squares scale at (m, m-1), formed on values scaled by t so
+       that the squares cannot underflow */
+    double t = fabs(f[m]) > fabs(f[m - 1]) ? fabs(f[m]) : fabs(f[m - 1]);
+    double fa = f[m] / t, fb = f[m - 1] / t;
+    double s = (fa * um + fb * um1) / (fa * fa + fb * fb);
+    int lhi = ls < lmax ? ls : lmax;
+    for (int l = nup + 1; l <= lhi; ++l) {
+        double v = s * (f[l] / t);
+        j[l] = (fabs(v) < 1e-300) ? 0.0 : v;
+    }
+}
+
+int or_sph_bessel_table(int lmax, int64_t nx, const double *x, double *J)
+{
+    double xmax = 0.0;
+    for (int64_t i = 0; i < nx; ++i) {
+        if (!(x[i] >= 0.0)) return -1;
+        if (x[i] > xmax) xmax = x[i];
+    }
+    int topmax = (int)ceil(xmax + 20.0 * cbrt(xmax) + 50.0) + lmax + 4;
+    int bad = 0;
+    #pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * (size_t)(topmax + 2));
+        if (!work) {
+            #pragma omp atomic write
+            bad = 1;
+        } else {
+            #pragma omp for schedule(dynamic, 64)
+            for (int64_t i = 0; i < nx; ++i)
+                or_sph_bessel_one(lmax, x[i], J + (size_t)i * (lmax + 1), work);
+            free(work);
+        }
+    }
+    return bad ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* beta_p(l, r) = (2/pi) Sum_k wk_k k^2 q_p(k) Delta_l(k) j_l(k r)     */
+/* (Appendix, definition of qt_i(x,l); the k integral is the given     */
+/* discrete rule).  Output beta[s][l - lmin][r] for the selected p.    */
+/* ------------------------------------------------------------------ */
+int or_beta(int lmin, int lmax, int nk, const double *k, const double *wk,
+            int nr, const double *r, int np, const double *qk, const double *delta,
+            int nsel, const int32_t *psel, double *beta)
+{
+    int L = lmax - lmin + 1;
+    for (int s = 0; s < nsel; ++s) if (psel[s] < 0 || psel[s] >= np) return -1;
+    memset(beta, 0, sizeof(double) * (size_t)nsel * L * nr);
+    int bad = 0;
+    #pragma omp parallel
+    {
+        double *jl = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        double xmax = k[nk - 1] * r[nr - 1];
+        for (int i = 0; i < nk; ++i) for (int q = 0; q < nr; ++q)
+            if (k[i] * r[q] > xmax) xmax = k[i] * r[q];
+        int topmax = (int)ceil(xmax + 20.0 * cbrt(xmax) + 50.0) + lmax + 4;
+        double *work = (double *)malloc(sizeof(double) * (size_t)(topmax + 2));
+        if (!jl || !work) {
+            #pragma omp atomic write
+            bad = 1;
+        } else {
+            #pragma omp for schedule(dynamic, 1)
+            for (int q = 0; q < nr; ++q) {
+                for (int i = 0; i < nk; ++i) {
+                    or_sph_bessel_one(lmax, k[i] * r[q], jl, work);
+                    double base = 2.0 / OR_PI * wk[i] * k[i] * k[i];
+                    for (int s = 0; s < nsel; ++s) {
+                        double qv = base * qk[(size_t)psel[s] * nk + i];
+                        double *b = beta + (size_t)s * L * nr;
+                        for (int l = lmin; l <= lmax; ++l)
+                            b[(size_t)(l - lmin) * nr + q] += qv * delta[(size_t)(l - lmin) * nk + i] * jl[l];
+                    }
+                }
+            }
+        }
+        free(jl);
+        free(work);
+    }
+    return bad ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* S_ap(r, mu) = Sum_l w_l qbar_a(l) beta_p(l, r) P_l(mu),              */
+/* w_l = (2l+1)^(1 - v_power) / sqrt(C_l)   (Sec. 2.2, Eq. (legendre);  */
+/* Appendix, v_l = (2l+1)^(1/6)).                                       */
+/* pairs[2*s] = a, pairs[2*s+1] = index into beta's first axis.         */
+/* P is the table from or_legendre_table (P[j][l], l = 0..lmax).        */
+/* Output S[s][r][mu].                                                  */
+/* ------------------------------------------------------------------ */
+int or_S(int lmin, int lmax, const double *cl, double v_power, int na, const double *ql,
+         int nr, int nmu, const double *P, int nb, const double *beta,
+         int npairs, const int32_t *pairs, double *S)
+{
+    int L = lmax - lmin + 1;
+    for (int s = 0; s < npairs; ++s) {
+        if (pairs[2 * s] < 0 || pairs[2 * s] >= na) return -1;
+        if (pairs[2 * s + 1] < 0 || pairs[2 * s + 1] >= nb) return -1;
+    }
+    for (int l = 0; l < L; ++l) if (!(cl[l] > 0.0)) return -3;
+    double *wl = (double *)malloc(sizeof(double) * (size_t)L);
+    if (!wl) return -2;
+    for (int l = lmin; l <= lmax; ++l)
+        wl[l - lmin] = pow(2.0 * l + 1.0, 1.0 - v_power) / sqrt(cl[l - lmin]);
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int s = 0; s < npairs; ++s) {
+        for (int q = 0; q < nr; ++q) {
+            int a = pairs[2 * s], b = pairs[2 * s + 1];
+            for (int j = 0; j < nmu; ++j) {
+                const double *Pj = P + (size_t)j * (lmax + 1);
+                double acc = 0.0;
+                for (int l = lmin; l <= lmax; ++l)
+                    acc += wl[l - lmin] * ql[(size_t)a * L + (l - lmin)]
+                         * beta[((size_t)b * L + (l - lmin)) * nr + q] * Pj[l];
+                S[((size_t)s * nr + q) * nmu + j] = acc;
+            }
+        }
+    }
+    free(wl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Gamma entries (Sec. 2.2, Eq. (2D)).  For entry e, sidx[9*e + 3*s + t] */
+/* is the index (into S's first axis) of S_{a_s p_t}.                    */
+/*   kind 0 (ordered):   F = S_{a1p1} S_{a2p2} S_{a3p3},   c = 1/(8 pi)  */
+/*   kind 1 (symmetric): F = permanent of [S_{a_s p_t}],  c = 1/(48 pi)  */
+/* Gamma_e = c Sum_r wr_r r^2 [ Sum_mu wmu_mu F(r, mu) ]: the mu sum is  */
+/* completed for each r before the r sum (Sec. 2.2).                     */
+/* ------------------------------------------------------------------ */
+int or_gamma_entries(int kind, int nr, const double *r, const double *wr,
+                     int nmu, const double *wmu, int nS, const double *S,
+                     int64_t ne, const int32_t *sidx, double *gamma)
+{
+    for (int64_t e = 0; e < 9 * ne; ++e) if (sidx[e] < 0 || sidx[e] >= nS) return -1;
+    double c = (kind == 0) ? 1.0 / (8.0 * OR_PI) : 1.0 / (48.0 * OR_PI);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t e = 0; e < ne; ++e) {
+        const int32_t *ix = sidx + 9 * e;
+        double outer = 0.0;
+        for (int q = 0; q < nr; ++q) {
+            const double *m[3][3];
+            for (int s = 0; s < 3; ++s)
+                for (int t = 0; t < 3; ++t)
+                    m[s][t] = S + ((size_t)ix[3 * s + t] * nr + q) * nmu;
+            double inner = 0.0;
+            for (int j = 0; j < nmu; ++j) {
+                double F;
+                if (kind == 0) {
+                    F = m[0][0][j] * m[1][1][j] * m[2][2][j];
+                } else {
+                    F = m[0][0][j] * m[1][1][j] * m[2][2][j]
+                      + m[0][0][j] * m[1][2][j] * m[2][1][j]
+                      + m[0][1][j] * m[1][0][j] * m[2][2][j]
+                      + m[0][1][j] * m[1][2][j] * m[2][0][j]
+                      + m[0][2][j] * m[1][0][j] * m[2][1][j]
+                      + m[0][2][j] * m[1][1][j] * m[2][0][j];
+                }
+                inner += wmu[j] * F;
+            }
+            outer += wr[q] * r[q] * r[q] * inner;
+        }
+        gamma[e] = c * outer;
+    }
+    return 0;
+}
+
+int or_num_threads(void)
+{
+    int n = 1;
+    #pragma omp parallel
+    {
+        #pragma omp single
+        {
+#ifdef _OPENMP
+            extern int omp_get_num_threads(void);
+            n = omp_get_num_threads();
+#endif
+        }
+    }
+    return n;
+}

@@ -1,0 +1,275 @@
+"""Python face of the test oracle for the separable bispectrum projection.
+
+TEST INFRASTRUCTURE ONLY: the product path never imports this module.
+Only tests, the smoke check and the CPU-baseline leg of the benchmark use
+it.  It shares no code with the HIP library (the seeded inputs it is fed
+come from their own module, which holds none of the method's arithmetic).
+
+The numerical work is in ``modal_oracle.c`` (plain FP64 loops); this file
+marshals arrays, selects what a sampled entry needs, and holds the
+brute-force exact-3j form of the inner product used to pin the separable
+oracle (Sec. 2.1, Eq. (weight-function) and Eq. (3D) with the exact
+Wigner symbol in place of the Gosper approximation).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "modal_oracle.c")
+_LIB = os.path.join(_HERE, "libmodal_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.or_gauss_legendre.argtypes = [ctypes.c_int, _dp, _dp]
+        L.or_legendre_table.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+        L.or_sph_bessel_table.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, _dp]
+        L.or_beta.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
+                              ctypes.c_int, _dp, _dp, ctypes.c_int, _ip, _dp]
+        L.or_S.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, _dp,
+                           ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_int, _ip, _dp]
+        L.or_gamma_entries.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
+                                       ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp]
+        L.or_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+# ---------------------------------------------------------------- stages
+def gauss_legendre(n: int):
+    """Gauss-Legendre nodes (ascending) and weights on [-1, 1] (Sec. 2.2)."""
+    x = np.empty(n)
+    w = np.empty(n)
+    _check(lib().or_gauss_legendre(n, x.ctypes.data_as(_dp), w.ctypes.data_as(_dp)), "gl")
+    return x, w
+
+
+def legendre_table(lmax: int, mu) -> np.ndarray:
+    """P[j][l] = P_l(mu_j), l = 0..lmax."""
+    mu, pm = _d(mu)
+    P = np.empty((mu.size, lmax + 1))
+    lib().or_legendre_table(lmax, mu.size, pm, P.ctypes.data_as(_dp))
+    return P
+
+
+def sph_bessel_table(lmax: int, x) -> np.ndarray:
+    """J[i][l] = j_l(x_i), l = 0..lmax (Appendix: projection kernel)."""
+    x, px = _d(x)
+    J = np.empty((x.size, lmax + 1))
+    _check(lib().or_sph_bessel_table(lmax, x.size, px, J.ctypes.data_as(_dp)), "sph_bessel")
+    return J
+
+
+def beta(inp, psel=None) -> np.ndarray:
+    """beta[s][l - lmin][r] for p = psel[s] (Appendix, projected modes, x 2/pi)."""
+    c = inp.cfg
+    if psel is None:
+        psel = np.arange(inp.qk.shape[0])
+    psel, pp = _i(psel)
+    k, kp = _d(inp.k)
+    wk, wkp = _d(inp.wk)
+    r, rp = _d(inp.r)
+    qk, qp = _d(inp.qk)
+    de, dp = _d(inp.delta)
+    out = np.empty((psel.size, c.L, r.size))
+    _check(lib().or_beta(c.lmin, c.lmax, k.size, kp, wkp, r.size, rp, qk.shape[0], qp, dp,
+                         psel.size, pp, out.ctypes.data_as(_dp)), "beta")
+    return out
+
+
+def weights_l(inp) -> np.ndarray:
+    """w_l = (2l+1)^(1 - v_power) / sqrt(C_l) (Sec. 2.2, Eq. (legendre))."""
+    l = inp.ells.astype(np.float64)
+    return (2 * l + 1) ** (1.0 - inp.cfg.v_power) / np.sqrt(inp.cl)
+
+
+def S_pairs(inp, mu, beta_arr, pairs) -> np.ndarray:
+    """S[s][r][mu] = S_{a p}(r, mu) for (a, b) = pairs[s], b indexing beta_arr."""
+    c = inp.cfg
+    P = legendre_table(c.lmax, mu)
+    pairs, pr = _i(np.asarray(pairs).reshape(-1, 2))
+    cl, clp = _d(inp.cl)
+    ql, qlp = _d(inp.ql)
+    b, bp = _d(beta_arr)
+    Pm, Pp = _d(P)
+    out = np.empty((pairs.shape[0], c.nr, len(mu)))
+    _check(lib().or_S(c.lmin, c.lmax, clp, c.v_power, ql.shape[0], qlp, c.nr, len(mu), Pp,
+                      b.shape[0], bp, pairs.shape[0], pr, out.ctypes.data_as(_dp)), "S")
+    return out
+
+
+def _kind_code(kind: str) -> int:
+    return 0 if kind == "ordered" else 1
+
+
+def gamma_from_S(inp, wmu, S_arr, sidx) -> np.ndarray:
+    """Gamma entries from an S stack and per-entry 3x3 index blocks (Eq. (2D))."""
+    c = inp.cfg
+    S_arr, sp_ = _d(S_arr)
+    sidx, sip = _i(np.asarray(sidx).reshape(-1, 9))
+    r, rp = _d(inp.r)
+    wr, wrp = _d(inp.wr)
+    wmu, wmp = _d(wmu)
+    out = np.empty(sidx.shape[0])
+    _check(lib().or_gamma_entries(_kind_code(c.kind), c.nr, rp, wrp, wmu.size, wmp,
+                                  S_arr.shape[0], sp_, sidx.shape[0], sip,
+                                  out.ctypes.data_as(_dp)), "gamma")
+    return out
+
+
+def gamma_entries(inp, rows, cols, mu=None, wmu=None, return_S=False):
+    """Gamma[tri_a[rows[e]], tri_p[cols[e]]] computed one entry at a time.
+
+    Only the beta rows and S pairs the requested entries touch are formed.
+    """
+    c = inp.cfg
+    if mu is None:
+        mu, wmu = gauss_legendre(c.nmu)
+    rows = np.asarray(rows, dtype=np.int64).ravel()
+    cols = np.asarray(cols, dtype=np.int64).ravel()
+    ta = inp.tri_a[rows]
+    tp = inp.tri_p[cols]
+    pset = np.unique(tp)
+    bet = beta(inp, pset)
+    ppos = {int(p): i for i, p in enumerate(pset)}
+    need = {}
+    for e in range(rows.size):
+        for s in range(3):
+            for t in range(3):
+                need.setdefault((int(ta[e, s]), int(tp[e, t])), len(need))
+    pairs = np.array([(a, ppos[p]) for (a, p) in need], dtype=np.int32)
+    S_arr = S_pairs(inp, mu, bet, pairs)
+    sidx = np.empty((rows.size, 9), dtype=np.int32)
+    for e in range(rows.size):
+        for s in range(3):
+            for t in range(3):
+                sidx[e, 3 * s + t] = need[(int(ta[e, s]), int(tp[e, t]))]
+    g = gamma_from_S(inp, wmu, S_arr, sidx)
+    if return_S:
+        return g, S_arr, need
+    return g
+
+
+def gamma_full(inp, mu=None, wmu=None) -> np.ndarray:
+    """The whole Gamma[tri_a][tri_p] (small workloads only)."""
+    c = inp.cfg
+    if mu is None:
+        mu, wmu = gauss_legendre(c.nmu)
+    na, npm = inp.ql.shape[0], inp.qk.shape[0]
+    bet = beta(inp)
+    pairs = np.array([(a, p) for a in range(na) for p in range(npm)], dtype=np.int32)
+    S_arr = S_pairs(inp, mu, bet, pairs)
+    ta, tp = inp.tri_a, inp.tri_p
+    A = ta[:, None, :, None] * npm                    # [ta][1][3][1]
+    P = tp[None, :, None, :]                          # [1][tp][1][3]
+    sidx = (A + P).reshape(-1, 9)
+    return gamma_from_S(inp, wmu, S_arr, sidx).reshape(ta.shape[0], tp.shape[0])
+
+
+def full_S(inp, mu):
+    """S[a][p][r][mu] for all pairs (small workloads only)."""
+    na, npm = inp.ql.shape[0], inp.qk.shape[0]
+    bet = beta(inp)
+    pairs = np.array([(a, p) for a in range(na) for p in range(npm)], dtype=np.int32)
+    return S_pairs(inp, mu, bet, pairs).reshape(na, npm, inp.cfg.nr, len(mu)), bet
+
+
+# ------------------------------------------------- exact 3j and brute force
+def threej000_sq(l1: int, l2: int, l3: int) -> float:
+    """(l1 l2 l3; 0 0 0)^2 from its closed form in factorials, in exact
+    integer arithmetic, rounded once to double.  Zero unless the triangle
+    and parity conditions hold (Sec. 2.1)."""
+    L = l1 + l2 + l3
+    if L % 2 or l3 > l1 + l2 or l1 > l2 + l3 or l2 > l1 + l3:
+        return 0.0
+    g = L // 2
+    f = math.factorial
+    num = f(L - 2 * l1) * f(L - 2 * l2) * f(L - 2 * l3) * f(g) ** 2
+    den = f(L + 1) * (f(g - l1) * f(g - l2) * f(g - l3)) ** 2
+    return num / den
+
+
+def brute_force_gamma_ordered(inp, beta_arr=None) -> np.ndarray:
+    """Ordered Gamma from the inner product of Sec. 2.1 with the exact
+    Wigner symbol: a direct sum over every ordered (l1, l2, l3) in
+    [lmin, lmax]^3 of
+
+        C(l1,l2,l3) * prod_s qbar_{a_s}(l_s) * Sum_r wr r^2 prod_s beta_{p_s}(l_s, r),
+        C = 2 (l1 l2 l3; 000)^2 / (8 pi) * w_l1 w_l2 w_l3
+
+    (h^2 / (v1 v2 v3)^2 * v1 v2 v3 / sqrt(C1 C2 C3) with
+    h^2 = prod(2l+1)/(4 pi) (3j)^2 gives the 2/(8 pi) and w_l).  No
+    Legendre polynomials and no mu quadrature appear.  The triple sum is
+    evaluated, for each r, as three successive tensordot contractions of
+    the dense coefficient tensor C with U_r[l, (a, p)] = qbar_a(l) beta_p(l, r).
+    Only the ordered-triple lists of an ordered workload are supported.
+    """
+    c = inp.cfg
+    if beta_arr is None:
+        beta_arr = beta(inp)
+    L = c.L
+    C = np.zeros((L, L, L))
+    cache = {}
+    for i1 in range(L):
+        for i2 in range(L):
+            for i3 in range(L):
+                key = tuple(sorted((i1 + c.lmin, i2 + c.lmin, i3 + c.lmin)))
+                if key not in cache:
+                    cache[key] = threej000_sq(*key)
+                C[i1, i2, i3] = cache[key]
+    w = weights_l(inp)
+    C *= 2.0 / (8.0 * math.pi) * w[:, None, None] * w[None, :, None] * w[None, None, :]
+    na, npm = inp.ql.shape[0], beta_arr.shape[0]
+    G = np.zeros((na, npm, na, npm, na, npm))
+    for q in range(c.nr):
+        U = inp.ql.T[:, :, None] * beta_arr[:, :, q].T[:, None, :]     # [l][a][p]
+        T1 = np.tensordot(C, U, axes=([2], [0]))                        # [l1][l2][a3][p3]
+        T2 = np.tensordot(T1, U, axes=([1], [0]))                       # [l1][a3][p3][a2][p2]
+        T3 = np.tensordot(U, T2, axes=([0], [0]))                       # [a1][p1][a3][p3][a2][p2]
+        G += inp.wr[q] * inp.r[q] ** 2 * T3.transpose(0, 1, 4, 5, 2, 3)
+    G = G.reshape(na, npm, na, npm, na, npm)
+    ta, tp = inp.tri_a, inp.tri_p
+    return G[ta[:, 0][:, None], tp[:, 0][None, :], ta[:, 1][:, None], tp[:, 1][None, :],
+             ta[:, 2][:, None], tp[:, 2][None, :]]
