@@ -1,0 +1,204 @@
+/*
+ * modalproj.h -- C ABI of the MI355X separable bispectrum projection.
+ *
+ * The library computes the matrix Gamma' of the separable ("2D") form of
+ * the modal projection: Sec. 2.2, Eq. (2D) with P_ii'(r, mu) from
+ * Eq. (legendre), and the projected primordial modes of the Appendix
+ * (qt_i(r, l) = Int dk k^2 qbar_i(k) Delta_l(k) j_l(k r)).  Names used in
+ * this header:
+ *
+ *   q_p(k)      primordial 1-D mode p  (the Appendix's qbar_i(k)), p < np
+ *   qbar_a(l)   late-time 1-D mode a   (the Appendix's q_i(l)),    a < na
+ *   beta_p(l,r) = (2/pi) Sum_k wk k^2 q_p(k) Delta_l(k) j_l(k r)
+ *               (the Appendix's qt_p(r, l), times 2/pi)
+ *   w_l         = (2l+1)^(1 - v_power) / sqrt(C_l); v_power = 1/6 gives
+ *               the (2l+1)/(v_l sqrt(C_l)) of Eq. (legendre) with
+ *               v_l = (2l+1)^(1/6) (Appendix)
+ *   S_ap(r,mu)  = Sum_l w_l qbar_a(l) beta_p(l, r) P_l(mu)
+ *               (Eq. (legendre)'s P_ii'(r, mu), a <-> i, p <-> i')
+ *   W(r,mu)     = wr_r r^2 wmu_mu   (the r^2 dr and dmu measures)
+ *
+ * and Gamma is returned in one of two forms:
+ *
+ *   ORDERED   Gamma[A][P] = 1/(8 pi) Sum_r Sum_mu W S_{a1p1} S_{a2p2} S_{a3p3}
+ *             for A = tri_a[row] = (a1,a2,a3), P = tri_p[col] = (p1,p2,p3)
+ *   SYMMETRIC Gamma[n][m] = 1/(48 pi) Sum_r Sum_mu W perm[S_{a_s p_t}]
+ *             (Eq. (2D): the six permutation products of the 3x3 block,
+ *             i.e. its permanent; repeated indices keep all six terms)
+ *
+ * The mu sum of every r is completed before it enters the r sum (Sec. 2.2).
+ * l runs over lmin..lmax (Eq. (3D) starts at l = 2); the arrays indexed
+ * by l hold L = lmax - lmin + 1 rows.
+ *
+ * Memory.  Every array argument may be host memory or device memory of the
+ * context's device; the library detects which.  All floating-point arrays
+ * are FP64, all index arrays int32, every layout row-major (C order).  The
+ * caller owns all inputs and outputs; the library keeps no pointer after a
+ * call returns.  Device-memory outputs are complete once the context's
+ * stream reaches the end of the call's work; host-memory outputs are
+ * complete when the call returns (the library synchronises the stream).
+ * The context owns a device workspace that grows on demand and is released
+ * by modal_destroy.
+ *
+ * Errors.  Nothing is thrown and nothing aborts across this boundary: each
+ * call returns a modal_status, and modal_last_error() gives a message for
+ * the last failing call on that context.  A context is not thread-safe;
+ * separate contexts are independent.
+ */
+#ifndef MODALPROJ_H
+#define MODALPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct modal_ctx_s *modal_ctx;
+
+typedef enum {
+    MODAL_OK = 0,
+    MODAL_ERR_INVALID_ARG = 1,   /* NULL pointer, bad enum, bad option        */
+    MODAL_ERR_SHAPE = 2,         /* sizes/indices out of range                 */
+    MODAL_ERR_OOM = 3,           /* device allocation failed or over the cap   */
+    MODAL_ERR_DEVICE = 4,        /* no usable device, or a HIP runtime error   */
+    MODAL_ERR_NUMERIC = 5,       /* non-positive C_l, non-finite input         */
+    MODAL_ERR_UNSUPPORTED = 6    /* valid request this build does not handle   */
+} modal_status;
+
+/* Arithmetic of the projection.
+ *   MODAL_FP64  : every stage in FP64 (j_l, P_l, beta, S, Gamma).
+ *   MODAL_MIXED : j_l, P_l, beta and S in FP64; the triple-product quadrature
+ *                 of Eq. (2D) on BF16 matrix cores with each operand split in
+ *                 a high and a low BF16 part (three products per term),
+ *                 FP32 accumulation of each r's mu sum and FP64 accumulation
+ *                 of the r sum. */
+typedef enum { MODAL_FP64 = 0, MODAL_MIXED = 1 } modal_precision;
+
+typedef enum { MODAL_GAMMA_ORDERED = 0, MODAL_GAMMA_SYMMETRIC = 1 } modal_gamma_kind;
+
+/* Quadrature grids.  k ascending > 0; r > 0.  wk and wr are the weights of
+ * the k and r rules (the r^2 of Eq. (2D) is applied by the library).  If
+ * mu and wmu are both NULL the library computes the nmu-point
+ * Gauss-Legendre rule itself.  Unless allow_inexact_gl is non-zero, nmu
+ * must be at least ceil((3 lmax + 1) / 2), the smallest rule that
+ * integrates P_l1 P_l2 P_l3 exactly (Sec. 2.2). */
+typedef struct {
+    int32_t lmin, lmax;
+    int32_t nk;
+    const double *k, *wk;      /* [nk] */
+    int32_t nr;
+    const double *r, *wr;      /* [nr] */
+    int32_t nmu;
+    const double *mu, *wmu;    /* [nmu] or both NULL */
+    int32_t allow_inexact_gl;
+} modal_grid;
+
+/* Transfer table, power spectrum, the two 1-D bases and the mode lists. */
+typedef struct {
+    const double *delta;       /* Delta_l(k)   [L][nk]                      */
+    const double *cl;          /* C_l          [L], every entry > 0         */
+    int32_t np;
+    const double *qk;          /* q_p(k)       [np][nk]                     */
+    int32_t na;
+    const double *ql;          /* qbar_a(l)    [na][L]                      */
+    double v_power;            /* exponent of v_l; 1/6 in the paper         */
+    int32_t kind;              /* modal_gamma_kind                          */
+    int32_t ta;
+    const int32_t *tri_a;      /* [ta][3] late-time triples, entries < na   */
+    int32_t tp;
+    const int32_t *tri_p;      /* [tp][3] primordial triples, entries < np  */
+} modal_problem;
+
+/* ------------------------------------------------------------------ */
+/* Context                                                            */
+/* ------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, enqueueing its work on
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream).
+ * Returns MODAL_ERR_DEVICE if the device cannot be used. */
+modal_status modal_create(modal_ctx *out, int device, void *hip_stream);
+
+/* Release the context and its workspace (waits for its stream). */
+modal_status modal_destroy(modal_ctx ctx);
+
+/* Change the stream later calls enqueue on. */
+modal_status modal_set_stream(modal_ctx ctx, void *hip_stream);
+
+/* Static text for a status code. */
+const char *modal_status_str(modal_status s);
+
+/* Message of the last failing call on ctx (on any context if ctx is NULL);
+ * valid until the next call on that context. */
+const char *modal_last_error(modal_ctx ctx);
+
+/* Cap on the workspace in bytes (0 = no cap).  A call that would need more
+ * returns MODAL_ERR_OOM. */
+modal_status modal_set_workspace_limit(modal_ctx ctx, size_t bytes);
+
+/* Device bytes the context would hold for modal_gamma on this problem. */
+modal_status modal_workspace_bytes(modal_ctx ctx, const modal_grid *grid,
+                                   const modal_problem *prob, modal_precision prec,
+                                   size_t *bytes);
+
+/* Stage timing.  When enabled, each later call records HIP events around
+ * its kernels on the context's stream; modal_stage_times then waits for the
+ * stream and reports the milliseconds of the last call's stages, in order
+ * MODAL_STAGE_GL, _LEGENDRE, _BESSEL, _BETA, _S, _TRIPLE, _GATHER (0 for a
+ * stage the call did not run).  n is the length of ms (>= MODAL_NSTAGES). */
+enum { MODAL_STAGE_GL = 0, MODAL_STAGE_LEGENDRE, MODAL_STAGE_BESSEL, MODAL_STAGE_BETA,
+       MODAL_STAGE_S, MODAL_STAGE_TRIPLE, MODAL_STAGE_GATHER, MODAL_NSTAGES };
+modal_status modal_enable_timing(modal_ctx ctx, int on);
+modal_status modal_stage_times(modal_ctx ctx, double *ms, int n);
+
+/* ------------------------------------------------------------------ */
+/* Stage entry points (step a)                                        */
+/* ------------------------------------------------------------------ */
+
+/* n-point Gauss-Legendre rule on [-1, 1] (Sec. 2.2: exact for the
+ * polynomial mu integrand).  x ascending, x[i] = -x[n-1-i]; w > 0.
+ * x, w: [n].  n >= 1. */
+modal_status modal_gauss_legendre(modal_ctx ctx, int32_t n, double *x, double *w);
+
+/* Legendre table P[l][j] = P_l(mu_j), l = 0..lmax, j < nmu (the P_l(mu) of
+ * Eq. (legendre)).  mu: [nmu] in [-1, 1]; P: [lmax+1][nmu]. */
+modal_status modal_legendre_table(modal_ctx ctx, int32_t lmax, int32_t nmu,
+                                  const double *mu, double *P);
+
+/* Spherical Bessel table J[l][i] = j_l(x_i), l = 0..lmax (the j_l(kr) of
+ * the projected modes, Appendix).  x: [nx], every x_i >= 0;
+ * J: [lmax+1][nx]. */
+modal_status modal_sph_bessel_table(modal_ctx ctx, int32_t lmax, int64_t nx,
+                                    const double *x, double *J);
+
+/* ------------------------------------------------------------------ */
+/* Stage entry points (steps b, c, d)                                 */
+/* ------------------------------------------------------------------ */
+
+/* beta_p(l, r) (Appendix, projected modes, times 2/pi).
+ * beta: [np][L][nr].  Uses grid k, wk, r and prob delta, qk. */
+modal_status modal_beta(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
+                        modal_precision prec, double *beta);
+
+/* S_ap(r, mu) of Eq. (legendre) from a given beta ([np][L][nr]).
+ * S: [na][np][nr][nmu]. */
+modal_status modal_S(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
+                     modal_precision prec, const double *beta, double *S);
+
+/* Gamma of Eq. (2D) (ordered or symmetric, per prob->kind) from a given S
+ * ([na][np][nr][nmu]).  gamma: [ta][tp]. */
+modal_status modal_gamma_from_S(modal_ctx ctx, const modal_grid *grid,
+                                const modal_problem *prob, modal_precision prec,
+                                const double *S, double *gamma);
+
+/* The whole projection: grids -> P_l, j_l -> beta -> S -> Gamma.
+ * gamma: [ta][tp]. */
+modal_status modal_gamma(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
+                         modal_precision prec, double *gamma);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MODALPROJ_H */

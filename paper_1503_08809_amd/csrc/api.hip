@@ -1,0 +1,737 @@
+// C ABI of the separable projection: argument checks, workspace, host/device
+// staging, and the order of the stages (Sec. 2.2, Eq. (2D) and
+// Eq. (legendre); Appendix, projected modes).  No exception or abort crosses
+// the boundary: every entry point returns a modal_status.
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+
+using namespace mp;
+
+namespace {
+
+thread_local std::string g_last_error;   // for calls without a usable context
+
+enum Slot {
+    W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
+    W_S32, W_SH, W_SL, W_GAMMA, W_IN0, NSLOTS = W_IN0 + 16
+};
+
+struct Buf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct modal_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    Buf ws[NSLOTS];
+    size_t limit = 0;
+    int next_in = 0;
+    TriplePlan plan;
+    bool timing = false;
+    // per stage: a pool of (start, end) event pairs; the first `used` belong
+    // to the last call (chunked stages record one pair per chunk)
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MODAL_NSTAGES];
+    int used[MODAL_NSTAGES] = {};
+};
+
+namespace {
+
+struct Fail {
+    modal_status st;
+};
+
+[[noreturn]] void fail(modal_ctx c, modal_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    g_last_error = msg;
+    throw Fail{st};
+}
+
+void hipck(modal_ctx c, hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        const modal_status st = (e == hipErrorOutOfMemory) ? MODAL_ERR_OOM : MODAL_ERR_DEVICE;
+        fail(c, st, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+size_t held_bytes(modal_ctx c)
+{
+    size_t s = 0;
+    for (auto &b : c->ws) s += b.n;
+    return s;
+}
+
+void *ws_get(modal_ctx c, int slot, size_t bytes)
+{
+    Buf &b = c->ws[slot];
+    if (bytes == 0) bytes = 8;
+    if (b.n >= bytes) return b.p;
+    if (c->limit && held_bytes(c) - b.n + bytes > c->limit)
+        fail(c, MODAL_ERR_OOM, "workspace limit exceeded (" + std::to_string(bytes) + " bytes requested)");
+    if (b.p) {
+        hipck(c, hipStreamSynchronize(c->stream), "sync before realloc");
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(c, MODAL_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    b.p = p;
+    b.n = bytes;
+    return p;
+}
+
+// Device-visible copy of a caller array (the caller's pointer itself if it is
+// device memory of this context's device).
+bool is_device_ptr(modal_ctx c, const void *p)
+{
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) {
+        if (a.device != c->device) fail(c, MODAL_ERR_INVALID_ARG, "device pointer of another device");
+        return true;
+    }
+    return false;
+}
+
+template <class T>
+const T *dev_in(modal_ctx c, const T *p, size_t count)
+{
+    if (!p || count == 0) return p;
+    if (is_device_ptr(c, p)) return p;
+    if (c->next_in >= 16) fail(c, MODAL_ERR_INVALID_ARG, "too many host inputs");
+    T *d = (T *)ws_get(c, W_IN0 + c->next_in++, sizeof(T) * count);
+    hipck(c, hipMemcpyAsync(d, p, sizeof(T) * count, hipMemcpyHostToDevice, c->stream), "H2D");
+    return d;
+}
+
+template <class T>
+std::vector<T> host_copy(modal_ctx c, const T *p, size_t count)
+{
+    std::vector<T> v(count);
+    if (count == 0) return v;
+    if (is_device_ptr(c, p)) {
+        hipck(c, hipMemcpyAsync(v.data(), p, sizeof(T) * count, hipMemcpyDeviceToHost, c->stream), "D2H");
+        hipck(c, hipStreamSynchronize(c->stream), "sync");
+    } else {
+        std::memcpy(v.data(), p, sizeof(T) * count);
+    }
+    return v;
+}
+
+struct OutBuf {
+    double *dev = nullptr;
+    double *host = nullptr;
+    size_t count = 0;
+};
+
+OutBuf dev_out(modal_ctx c, double *p, size_t count, int slot)
+{
+    OutBuf o;
+    o.count = count;
+    if (count == 0) {
+        o.dev = p;
+        return o;
+    }
+    if (is_device_ptr(c, p)) {
+        o.dev = p;
+    } else {
+        o.host = p;
+        o.dev = (double *)ws_get(c, slot, sizeof(double) * count);
+    }
+    return o;
+}
+
+void finish_out(modal_ctx c, const OutBuf &o)
+{
+    if (o.host && o.count) {
+        hipck(c, hipMemcpyAsync(o.host, o.dev, sizeof(double) * o.count, hipMemcpyDeviceToHost, c->stream),
+              "D2H");
+        hipck(c, hipStreamSynchronize(c->stream), "sync");
+    }
+}
+
+struct StageTimer {
+    modal_ctx c;
+    int st;
+    hipEvent_t end = nullptr;
+    StageTimer(modal_ctx c_, int s) : c(c_), st(s)
+    {
+        if (!c->timing) return;
+        auto &pool = c->ev[st];
+        if (c->used[st] == (int)pool.size()) {
+            hipEvent_t a = nullptr, b = nullptr;
+            hipck(c, hipEventCreate(&a), "event create");
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                fail(c, MODAL_ERR_DEVICE, "event create");
+            }
+            pool.emplace_back(a, b);
+        }
+        auto &pr = pool[c->used[st]++];
+        hipck(c, hipEventRecord(pr.first, c->stream), "event");
+        end = pr.second;
+    }
+    ~StageTimer()
+    {
+        if (end) (void)hipEventRecord(end, c->stream);
+    }
+};
+
+// Fill kernel (no memset nodes: callers may capture these streams).
+__global__ void k_zero(double *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+void zero(modal_ctx c, double *p, int64_t n)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p, n);
+    hipck(c, hipGetLastError(), "zero fill");
+}
+
+// ---- validation -------------------------------------------------------------
+struct Dims {
+    int L, nk, nr, nmu, ldmu, np, na, U;
+};
+
+void need(modal_ctx c, bool ok, modal_status st, const char *msg)
+{
+    if (!ok) fail(c, st, msg);
+}
+
+Dims check_grid(modal_ctx c, const modal_grid *g, bool need_mu_rule)
+{
+    need(c, g != nullptr, MODAL_ERR_INVALID_ARG, "grid is NULL");
+    need(c, g->lmin >= 0 && g->lmax >= g->lmin, MODAL_ERR_SHAPE, "need 0 <= lmin <= lmax");
+    need(c, g->lmax <= 20000, MODAL_ERR_SHAPE, "lmax above 20000");
+    need(c, g->nk >= 1 && g->nr >= 1 && g->nmu >= 1, MODAL_ERR_SHAPE, "nk, nr, nmu must be >= 1");
+    need(c, g->k && g->wk && g->r && g->wr, MODAL_ERR_INVALID_ARG, "k, wk, r, wr must be non-NULL");
+    need(c, (g->mu == nullptr) == (g->wmu == nullptr), MODAL_ERR_INVALID_ARG,
+         "mu and wmu must both be given or both be NULL");
+    if (need_mu_rule && !g->allow_inexact_gl) {
+        const int64_t nmin = (3 * (int64_t)g->lmax + 2) / 2;     // ceil((3 lmax + 1) / 2)
+        need(c, g->nmu >= nmin, MODAL_ERR_SHAPE,
+             "nmu below ceil((3 lmax + 1)/2): the mu rule would not be exact (set allow_inexact_gl)");
+    }
+    {
+        auto hk = host_copy(c, g->k, (size_t)g->nk);
+        auto hr = host_copy(c, g->r, (size_t)g->nr);
+        double km = 0.0, rm = 0.0;
+        for (double v : hk) {
+            need(c, v > 0.0 && std::isfinite(v), MODAL_ERR_NUMERIC, "k must be finite and > 0");
+            km = std::max(km, v);
+        }
+        for (double v : hr) {
+            need(c, v > 0.0 && std::isfinite(v), MODAL_ERR_NUMERIC, "r must be finite and > 0");
+            rm = std::max(rm, v);
+        }
+        need(c, km * rm < 1e6, MODAL_ERR_SHAPE, "k r above 1e6: Bessel recurrence range not supported");
+    }
+    Dims d{};
+    d.L = g->lmax - g->lmin + 1;
+    d.nk = g->nk;
+    d.nr = g->nr;
+    d.nmu = g->nmu;
+    d.ldmu = pad_to(g->nmu, kMuPad);
+    return d;
+}
+
+void check_problem(modal_ctx c, const modal_problem *p, Dims &d, bool need_delta, bool need_tri)
+{
+    need(c, p != nullptr, MODAL_ERR_INVALID_ARG, "problem is NULL");
+    need(c, p->np >= 1 && p->na >= 1, MODAL_ERR_SHAPE, "np and na must be >= 1");
+    need(c, (int64_t)p->np * p->na <= 8192, MODAL_ERR_SHAPE, "np * na above 8192");
+    need(c, p->cl && p->ql, MODAL_ERR_INVALID_ARG, "cl and ql must be non-NULL");
+    if (need_delta) need(c, p->delta && p->qk, MODAL_ERR_INVALID_ARG, "delta and qk must be non-NULL");
+    need(c, std::isfinite(p->v_power), MODAL_ERR_NUMERIC, "v_power not finite");
+    d.np = p->np;
+    d.na = p->na;
+    d.U = p->np * p->na;
+    auto cl = host_copy(c, p->cl, (size_t)d.L);
+    for (double v : cl) need(c, v > 0.0 && std::isfinite(v), MODAL_ERR_NUMERIC, "C_l must be finite and > 0");
+    if (need_tri) {
+        need(c, p->kind == MODAL_GAMMA_ORDERED || p->kind == MODAL_GAMMA_SYMMETRIC, MODAL_ERR_INVALID_ARG,
+             "kind must be MODAL_GAMMA_ORDERED or MODAL_GAMMA_SYMMETRIC");
+        need(c, p->ta >= 0 && p->tp >= 0, MODAL_ERR_SHAPE, "ta, tp must be >= 0");
+        need(c, p->ta == 0 || p->tri_a, MODAL_ERR_INVALID_ARG, "tri_a is NULL");
+        need(c, p->tp == 0 || p->tri_p, MODAL_ERR_INVALID_ARG, "tri_p is NULL");
+        auto ta = host_copy(c, p->tri_a, (size_t)p->ta * 3);
+        for (int v : ta) need(c, v >= 0 && v < p->na, MODAL_ERR_SHAPE, "tri_a entry outside [0, na)");
+        auto tp = host_copy(c, p->tri_p, (size_t)p->tp * 3);
+        for (int v : tp) need(c, v >= 0 && v < p->np, MODAL_ERR_SHAPE, "tri_p entry outside [0, np)");
+    }
+}
+
+void check_prec(modal_ctx c, modal_precision prec)
+{
+    need(c, prec == MODAL_FP64 || prec == MODAL_MIXED, MODAL_ERR_INVALID_ARG, "unknown precision");
+}
+
+template <class F>
+modal_status guarded(modal_ctx c, F &&f)
+{
+    if (!c) {
+        g_last_error = "context is NULL";
+        return MODAL_ERR_INVALID_ARG;
+    }
+    c->next_in = 0;
+    try {
+        hipError_t e = hipSetDevice(c->device);
+        if (e != hipSuccess) fail(c, MODAL_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+        if (c->timing)
+            for (int s = 0; s < MODAL_NSTAGES; ++s) c->used[s] = 0;
+        f();
+        return MODAL_OK;
+    } catch (const Fail &x) {
+        return x.st;
+    } catch (const std::bad_alloc &) {
+        c->err = g_last_error = "host allocation failed";
+        return MODAL_ERR_OOM;
+    } catch (...) {
+        c->err = g_last_error = "internal error";
+        return MODAL_ERR_DEVICE;
+    }
+}
+
+// ---- shared pipeline pieces ---------------------------------------------------
+struct Grid {
+    const double *k, *wk, *r, *wr, *mu, *wmu;
+};
+
+Grid stage_grid(modal_ctx c, const modal_grid *g, const Dims &d)
+{
+    Grid G;
+    G.k = dev_in(c, g->k, d.nk);
+    G.wk = dev_in(c, g->wk, d.nk);
+    G.r = dev_in(c, g->r, d.nr);
+    G.wr = dev_in(c, g->wr, d.nr);
+    if (g->mu) {
+        G.mu = dev_in(c, g->mu, d.nmu);
+        G.wmu = dev_in(c, g->wmu, d.nmu);
+    } else {
+        StageTimer tm(c, MODAL_STAGE_GL);
+        double *mu = (double *)ws_get(c, W_MU, sizeof(double) * d.nmu);
+        double *wmu = (double *)ws_get(c, W_WMU, sizeof(double) * d.nmu);
+        hipck(c, launch_gauss_legendre(d.nmu, mu, wmu, c->stream), "gauss_legendre");
+        G.mu = mu;
+        G.wmu = wmu;
+    }
+    return G;
+}
+
+// beta[p][l][r] into `beta` (device).
+void run_beta(modal_ctx c, const modal_grid *g, const Dims &d, const Grid &G, const double *delta,
+              const double *qk, double *beta)
+{
+    const int64_t nitems = (int64_t)d.nk * d.nr;
+    BesselState st;
+    char *sb = (char *)ws_get(c, W_BSTATE, (size_t)nitems * 40);
+    st.f0 = (double *)sb;
+    st.f1 = st.f0 + nitems;
+    st.c = st.f1 + nitems;
+    st.e = (int *)(st.c + nitems);
+    st.efin = st.e + nitems;
+    const size_t per_l = (size_t)nitems * sizeof(double);
+    int cl = (int)std::max<size_t>(1, std::min<size_t>((size_t)d.L, ((size_t)512 << 20) / per_l));
+    double *jd = (double *)ws_get(c, W_JCHUNK, per_l * cl);
+    {
+        StageTimer tm(c, MODAL_STAGE_BESSEL);
+        hipck(c, launch_bessel_prepare(nitems, nullptr, G.k, d.nk, G.r, g->lmax, st, c->stream),
+              "bessel prepare");
+    }
+    for (int lhi = g->lmax; lhi >= g->lmin; lhi -= cl) {
+        const int llo = std::max(g->lmin, lhi - cl + 1);
+        {
+            StageTimer tm(c, MODAL_STAGE_BESSEL);
+            hipck(c, launch_bessel_chunk(nitems, nullptr, G.k, d.nk, G.r, lhi, llo, st, jd, nitems,
+                                         delta + (size_t)(llo - g->lmin) * d.nk, llo, c->stream),
+                  "bessel chunk");
+        }
+        StageTimer tm(c, MODAL_STAGE_BETA);
+        hipck(c, launch_beta_gemm(lhi - llo + 1, llo, g->lmin, d.L, d.nk, d.nr, d.np, jd, G.k, G.wk, qk,
+                                  beta, c->stream),
+              "beta gemm");
+    }
+}
+
+// rowscale pointer arithmetic above: the emit kernel indexes
+// rowscale[(l - lrow0) * nk + k] with lrow0 = llo, so the pointer is offset to
+// row llo of delta.
+
+void ensure_plan(modal_ctx c, int U)
+{
+    if (c->plan.U == U && c->plan.tasks) return;
+    std::string err;
+    hipck(c, hipStreamSynchronize(c->stream), "sync");
+    hipError_t e = build_triple_plan(U, c->plan, err);
+    if (e != hipSuccess) fail(c, e == hipErrorOutOfMemory ? MODAL_ERR_OOM : MODAL_ERR_DEVICE, err);
+}
+
+// Triple products from scaled rows St ([Upad][nr * ldmu]) and gather.
+void run_triple_gather(modal_ctx c, const modal_problem *p, const Dims &d, modal_precision prec,
+                       double *St, double *gamma)
+{
+    ensure_plan(c, d.U);
+    const int64_t ldz = (int64_t)d.nr * d.ldmu;
+    double *T = (double *)ws_get(c, W_T, sizeof(double) * (size_t)c->plan.tsize);
+    {
+        StageTimer tm(c, MODAL_STAGE_TRIPLE);
+        if (prec == MODAL_FP64) {
+            hipck(c, launch_triple_f64(c->plan, ldz, ldz, St, T, c->stream), "triple f64");
+        } else {
+            const size_t n = (size_t)c->plan.Upad * ldz;
+            float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * n);
+            uint16_t *sh = (uint16_t *)ws_get(c, W_SH, sizeof(uint16_t) * n);
+            uint16_t *sl = (uint16_t *)ws_get(c, W_SL, sizeof(uint16_t) * n);
+            hipError_t e = launch_split_bf16((int64_t)n, St, s32, sh, sl, c->stream);
+            if (e == hipErrorNotSupported) fail(c, MODAL_ERR_UNSUPPORTED, "mixed precision not built");
+            hipck(c, e, "split");
+            hipck(c, launch_triple_mixed(c->plan, ldz, d.nr, d.ldmu, s32, sh, sl, T, c->stream), "triple mixed");
+        }
+    }
+    const int *ta = dev_in(c, p->tri_a, (size_t)p->ta * 3);
+    const int *tp = dev_in(c, p->tri_p, (size_t)p->tp * 3);
+    if ((int64_t)p->ta * p->tp == 0) return;
+    StageTimer tm(c, MODAL_STAGE_GATHER);
+    hipck(c, launch_gather(p->kind, p->ta, p->tp, ta, tp, d.np, c->plan, T, gamma, c->stream), "gather");
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+modal_status modal_create(modal_ctx *out, int device, void *hip_stream)
+{
+    if (!out) {
+        g_last_error = "out is NULL";
+        return MODAL_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        g_last_error = "no HIP device available";
+        return MODAL_ERR_DEVICE;
+    }
+    if (device < 0 || device >= n) {
+        g_last_error = "device index out of range";
+        return MODAL_ERR_DEVICE;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        g_last_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return MODAL_ERR_DEVICE;
+    }
+    modal_ctx c = new (std::nothrow) modal_ctx_s;
+    if (!c) {
+        g_last_error = "host allocation failed";
+        return MODAL_ERR_OOM;
+    }
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return MODAL_OK;
+}
+
+modal_status modal_destroy(modal_ctx c)
+{
+    if (!c) return MODAL_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &b : c->ws) (void)hipFree(b.p);
+    free_triple_plan(c->plan);
+    for (auto &pool : c->ev)
+        for (auto &pr : pool) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    delete c;
+    return MODAL_OK;
+}
+
+modal_status modal_set_stream(modal_ctx c, void *hip_stream)
+{
+    if (!c) return MODAL_ERR_INVALID_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return MODAL_OK;
+}
+
+const char *modal_status_str(modal_status s)
+{
+    switch (s) {
+    case MODAL_OK: return "ok";
+    case MODAL_ERR_INVALID_ARG: return "invalid argument";
+    case MODAL_ERR_SHAPE: return "shape or index out of range";
+    case MODAL_ERR_OOM: return "out of device memory";
+    case MODAL_ERR_DEVICE: return "device or HIP runtime error";
+    case MODAL_ERR_NUMERIC: return "invalid numeric input";
+    case MODAL_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *modal_last_error(modal_ctx c)
+{
+    if (c) return c->err.c_str();
+    return g_last_error.c_str();
+}
+
+modal_status modal_set_workspace_limit(modal_ctx c, size_t bytes)
+{
+    if (!c) return MODAL_ERR_INVALID_ARG;
+    c->limit = bytes;
+    return MODAL_OK;
+}
+
+modal_status modal_enable_timing(modal_ctx c, int on)
+{
+    if (!c) return MODAL_ERR_INVALID_ARG;
+    c->timing = on != 0;
+    for (int s = 0; s < MODAL_NSTAGES; ++s) c->used[s] = 0;
+    return MODAL_OK;
+}
+
+modal_status modal_stage_times(modal_ctx c, double *ms, int n)
+{
+    if (!c || !ms || n < MODAL_NSTAGES) return MODAL_ERR_INVALID_ARG;
+    // not `guarded`: that would reset the per-call event counts
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->err = g_last_error = "stream synchronisation failed";
+        return MODAL_ERR_DEVICE;
+    }
+    for (int s = 0; s < MODAL_NSTAGES; ++s) {
+        ms[s] = 0.0;
+        if (!c->timing) continue;
+        for (int i = 0; i < c->used[s]; ++i) {
+            float v = 0.f;
+            if (hipEventElapsedTime(&v, c->ev[s][i].first, c->ev[s][i].second) != hipSuccess) {
+                c->err = g_last_error = "hipEventElapsedTime failed";
+                return MODAL_ERR_DEVICE;
+            }
+            ms[s] += v;
+        }
+    }
+    return MODAL_OK;
+}
+
+modal_status modal_workspace_bytes(modal_ctx c, const modal_grid *g, const modal_problem *p,
+                                   modal_precision prec, size_t *bytes)
+{
+    return guarded(c, [&] {
+        need(c, bytes != nullptr, MODAL_ERR_INVALID_ARG, "bytes is NULL");
+        check_prec(c, prec);
+        Dims d = check_grid(c, g, false);
+        check_problem(c, p, d, true, false);
+        const size_t Upad = (size_t)pad_to(d.U, kRowBlock);
+        const size_t z = (size_t)d.nr * d.ldmu;
+        const size_t nitems = (size_t)d.nk * d.nr;
+        size_t cl = std::max<size_t>(1, std::min<size_t>((size_t)d.L, ((size_t)512 << 20) / (nitems * 8)));
+        const size_t npairs = (size_t)d.U * (d.U + 1) / 2;
+        const size_t tsize = (npairs + 15) / 16 * ((size_t)d.U / 16 + 1) * 256;   // upper bound
+        size_t b = 0;
+        b += 2 * d.nmu * 8 + (size_t)d.L * d.ldmu * 8 + d.L * 8 + z * 8;
+        b += nitems * 40 + cl * nitems * 8 + (size_t)d.np * d.L * d.nr * 8;
+        b += Upad * z * 8 + tsize * 8;
+        if (prec == MODAL_MIXED) b += Upad * z * 8;
+        *bytes = b;
+    });
+}
+
+modal_status modal_gauss_legendre(modal_ctx c, int32_t n, double *x, double *w)
+{
+    return guarded(c, [&] {
+        need(c, n >= 1, MODAL_ERR_SHAPE, "n must be >= 1");
+        need(c, x && w, MODAL_ERR_INVALID_ARG, "x, w must be non-NULL");
+        OutBuf ox = dev_out(c, x, n, W_MU), ow = dev_out(c, w, n, W_WMU);
+        {
+            StageTimer tm(c, MODAL_STAGE_GL);
+            hipck(c, launch_gauss_legendre(n, ox.dev, ow.dev, c->stream), "gauss_legendre");
+        }
+        finish_out(c, ox);
+        finish_out(c, ow);
+    });
+}
+
+modal_status modal_legendre_table(modal_ctx c, int32_t lmax, int32_t nmu, const double *mu, double *P)
+{
+    return guarded(c, [&] {
+        need(c, lmax >= 0 && lmax <= 20000 && nmu >= 1, MODAL_ERR_SHAPE, "need 0 <= lmax <= 20000, nmu >= 1");
+        need(c, mu && P, MODAL_ERR_INVALID_ARG, "mu, P must be non-NULL");
+        const double *dmu = dev_in(c, mu, nmu);
+        OutBuf o = dev_out(c, P, (size_t)(lmax + 1) * nmu, W_P);
+        {
+            StageTimer tm(c, MODAL_STAGE_LEGENDRE);
+            hipck(c, launch_legendre_table(lmax, 0, nmu, nmu, dmu, o.dev, c->stream), "legendre");
+        }
+        finish_out(c, o);
+    });
+}
+
+modal_status modal_sph_bessel_table(modal_ctx c, int32_t lmax, int64_t nx, const double *x, double *J)
+{
+    return guarded(c, [&] {
+        need(c, lmax >= 0 && lmax <= 20000 && nx >= 1, MODAL_ERR_SHAPE, "need 0 <= lmax <= 20000, nx >= 1");
+        need(c, x && J, MODAL_ERR_INVALID_ARG, "x, J must be non-NULL");
+        auto hx = host_copy(c, x, (size_t)nx);
+        for (double v : hx)
+            need(c, v >= 0.0 && v < 1e6, MODAL_ERR_NUMERIC, "x must be finite, >= 0 and < 1e6");
+        const double *dx = dev_in(c, x, (size_t)nx);
+        BesselState st;
+        char *sb = (char *)ws_get(c, W_BSTATE, (size_t)nx * 40);
+        st.f0 = (double *)sb;
+        st.f1 = st.f0 + nx;
+        st.c = st.f1 + nx;
+        st.e = (int *)(st.c + nx);
+        st.efin = st.e + nx;
+        OutBuf o = dev_out(c, J, (size_t)(lmax + 1) * nx, W_JCHUNK);
+        StageTimer tm(c, MODAL_STAGE_BESSEL);
+        hipck(c, launch_bessel_prepare(nx, dx, nullptr, 1, nullptr, lmax, st, c->stream), "bessel prepare");
+        hipck(c, launch_bessel_chunk(nx, dx, nullptr, 1, nullptr, lmax, 0, st, o.dev, nx, nullptr, 0, c->stream),
+              "bessel emit");
+        finish_out(c, o);
+    });
+}
+
+modal_status modal_beta(modal_ctx c, const modal_grid *g, const modal_problem *p, modal_precision prec,
+                        double *beta)
+{
+    return guarded(c, [&] {
+        check_prec(c, prec);
+        need(c, beta != nullptr, MODAL_ERR_INVALID_ARG, "beta is NULL");
+        Dims d = check_grid(c, g, false);
+        check_problem(c, p, d, true, false);
+        Grid G = stage_grid(c, g, d);
+        const double *delta = dev_in(c, p->delta, (size_t)d.L * d.nk);
+        const double *qk = dev_in(c, p->qk, (size_t)d.np * d.nk);
+        OutBuf o = dev_out(c, beta, (size_t)d.np * d.L * d.nr, W_BETA);
+        run_beta(c, g, d, G, delta, qk, o.dev);
+        finish_out(c, o);
+    });
+}
+
+modal_status modal_S(modal_ctx c, const modal_grid *g, const modal_problem *p, modal_precision prec,
+                     const double *beta, double *S)
+{
+    return guarded(c, [&] {
+        check_prec(c, prec);
+        need(c, beta && S, MODAL_ERR_INVALID_ARG, "beta, S must be non-NULL");
+        Dims d = check_grid(c, g, false);
+        check_problem(c, p, d, false, false);
+        Grid G = stage_grid(c, g, d);
+        const double *dbeta = dev_in(c, beta, (size_t)d.np * d.L * d.nr);
+        const double *cl = dev_in(c, p->cl, (size_t)d.L);
+        const double *ql = dev_in(c, p->ql, (size_t)d.na * d.L);
+        double *P = (double *)ws_get(c, W_P, sizeof(double) * (size_t)d.L * d.nmu);
+        double *wl = (double *)ws_get(c, W_WL, sizeof(double) * d.L);
+        {
+            StageTimer tm(c, MODAL_STAGE_LEGENDRE);
+            hipck(c, launch_legendre_table(g->lmax, g->lmin, d.nmu, d.nmu, G.mu, P, c->stream), "legendre");
+        }
+        OutBuf o = dev_out(c, S, (size_t)d.U * d.nr * d.nmu, W_ST);
+        StageTimer tm(c, MODAL_STAGE_S);
+        hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, cl, wl, c->stream), "weights");
+        hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.nmu, d.L, wl, ql, dbeta, P, d.nmu, nullptr, o.dev,
+                               c->stream),
+              "S gemm");
+        finish_out(c, o);
+    });
+}
+
+modal_status modal_gamma_from_S(modal_ctx c, const modal_grid *g, const modal_problem *p,
+                                modal_precision prec, const double *S, double *gamma)
+{
+    return guarded(c, [&] {
+        check_prec(c, prec);
+        Dims d = check_grid(c, g, false);
+        check_problem(c, p, d, false, true);
+        need(c, S != nullptr, MODAL_ERR_INVALID_ARG, "S is NULL");
+        need(c, gamma != nullptr || (int64_t)p->ta * p->tp == 0, MODAL_ERR_INVALID_ARG, "gamma is NULL");
+        Grid G = stage_grid(c, g, d);
+        const double *dS = dev_in(c, S, (size_t)d.U * d.nr * d.nmu);
+        const int Upad = pad_to(d.U, kRowBlock);
+        const int64_t ldz = (int64_t)d.nr * d.ldmu;
+        double *wz = (double *)ws_get(c, W_WZ, sizeof(double) * ldz);
+        double *St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * ldz);
+        OutBuf o = dev_out(c, gamma, (size_t)p->ta * p->tp, W_GAMMA);
+        {
+            StageTimer tm(c, MODAL_STAGE_S);
+            hipck(c, launch_cbrt_weights(d.nr, d.nmu, d.ldmu, G.r, G.wr, G.wmu, wz, c->stream), "weights");
+            hipck(c, launch_s_import(d.U, d.nr, d.nmu, d.ldmu, dS, wz, St, c->stream), "S import");
+            zero(c, St + (size_t)d.U * ldz, (int64_t)(Upad - d.U) * ldz);
+        }
+        run_triple_gather(c, p, d, prec, St, o.dev);
+        finish_out(c, o);
+    });
+}
+
+modal_status modal_gamma(modal_ctx c, const modal_grid *g, const modal_problem *p, modal_precision prec,
+                         double *gamma)
+{
+    return guarded(c, [&] {
+        check_prec(c, prec);
+        Dims d = check_grid(c, g, true);
+        check_problem(c, p, d, true, true);
+        need(c, gamma != nullptr || (int64_t)p->ta * p->tp == 0, MODAL_ERR_INVALID_ARG, "gamma is NULL");
+        Grid G = stage_grid(c, g, d);
+        const double *delta = dev_in(c, p->delta, (size_t)d.L * d.nk);
+        const double *qk = dev_in(c, p->qk, (size_t)d.np * d.nk);
+        const double *cl = dev_in(c, p->cl, (size_t)d.L);
+        const double *ql = dev_in(c, p->ql, (size_t)d.na * d.L);
+        OutBuf o = dev_out(c, gamma, (size_t)p->ta * p->tp, W_GAMMA);
+
+        // (a) Legendre table at the nodes, weights
+        double *P = (double *)ws_get(c, W_P, sizeof(double) * (size_t)d.L * d.ldmu);
+        double *wl = (double *)ws_get(c, W_WL, sizeof(double) * d.L);
+        const int64_t ldz = (int64_t)d.nr * d.ldmu;
+        double *wz = (double *)ws_get(c, W_WZ, sizeof(double) * ldz);
+        {
+            StageTimer tm(c, MODAL_STAGE_LEGENDRE);
+            hipck(c, launch_legendre_table(g->lmax, g->lmin, d.nmu, d.ldmu, G.mu, P, c->stream), "legendre");
+        }
+        // (a, b) Bessel functions and the k contraction
+        double *beta = (double *)ws_get(c, W_BETA, sizeof(double) * (size_t)d.np * d.L * d.nr);
+        run_beta(c, g, d, G, delta, qk, beta);
+        // (c) the l contraction, scaled rows
+        const int Upad = pad_to(d.U, kRowBlock);
+        double *St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * ldz);
+        {
+            StageTimer tm(c, MODAL_STAGE_S);
+            hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, cl, wl, c->stream), "weights");
+            hipck(c, launch_cbrt_weights(d.nr, d.nmu, d.ldmu, G.r, G.wr, G.wmu, wz, c->stream), "cbrt weights");
+            hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.ldmu, d.L, wl, ql, beta, P, d.ldmu, wz, St,
+                                   c->stream),
+                  "S gemm");
+            zero(c, St + (size_t)d.U * ldz, (int64_t)(Upad - d.U) * ldz);
+        }
+        // (d) triple products and Gamma
+        run_triple_gather(c, p, d, prec, St, o.dev);
+        finish_out(c, o);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/modalproj.h"
+
+namespace mp {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Padding of the mu axis inside the library: each r holds a whole number of
+// 16-wide z chunks (zeros past nmu), so an r boundary never falls inside a
+// chunk of the triple-product kernels.
+constexpr int kMuPad = 32;
+inline int pad_to(int n, int m) { return (n + m - 1) / m * m; }
+
+struct Error {
+    modal_status st;
+    std::string msg;
+};
+
+// ---- launchers (one per kernel family) --------------------------------
+// Step a: grids and tables.
+hipError_t launch_gauss_legendre(int n, double *x, double *w, hipStream_t s);
+hipError_t launch_legendre_table(int lmax, int lout0, int nmu, int ld, const double *mu,
+                                 double *P, hipStream_t s);
+
+// Spherical Bessel functions by Miller's downward recurrence.  The x value of
+// item i is xs[i] (table mode) or k[i % nk] * r[i / nk] (beta mode, xs == NULL).
+struct BesselState {
+    double *f0, *f1;     // f_l and f_{l+1} at the next l to emit
+    int *e;              // rescale count at that point
+    double *c;           // normalisation in the final frame
+    int *efin;           // rescale count at l = 0
+};
+hipError_t launch_bessel_prepare(int64_t nitems, const double *xs, const double *k, int nk,
+                                 const double *r, int lfirst, BesselState st, hipStream_t s);
+// Emit l = lhi down to llo (inclusive) into out[(l - llo) * ld_l + i] scaled by
+// rowscale[(l - lrow0) * nk + i % nk] when rowscale != NULL.
+hipError_t launch_bessel_chunk(int64_t nitems, const double *xs, const double *k, int nk,
+                               const double *r, int lhi, int llo, BesselState st,
+                               double *out, int64_t ld_l, const double *rowscale, int lrow0,
+                               hipStream_t s);
+
+// Step b: beta[p][l - lmin][r] for l in [l0, l0 + nl) from the emitted chunk
+// Jd[l - l0][k][r] = Delta_l(k) j_l(k r).
+hipError_t launch_beta_gemm(int nl, int l0, int lmin, int L, int nk, int nr, int np,
+                            const double *Jd, const double *k, const double *wk,
+                            const double *qk, double *beta, hipStream_t s);
+
+// Step c: S rows.  Output row u = a * np + p holds, for each r, nmu values
+// (padded to ldmu; padded entries are zero).  If wz != NULL the output is
+// scaled by wz[r * ldmu + mu] (the cube root of the quadrature weight).
+hipError_t launch_s_gemm(int na, int np, int nr, int nmu, int ldmu, int L,
+                         const double *wl, const double *ql, const double *beta,
+                         const double *P, int ldP, const double *wz, double *S, hipStream_t s);
+hipError_t launch_weights_l(int L, int lmin, double v_power, const double *cl, double *wl,
+                            hipStream_t s);
+hipError_t launch_cbrt_weights(int nr, int nmu, int ldmu, const double *r, const double *wr,
+                               const double *wmu, double *wz, hipStream_t s);
+// S in the caller's layout [u][r][nmu] -> scaled, padded rows.
+hipError_t launch_s_import(int64_t nu, int nr, int nmu, int ldmu, const double *S,
+                           const double *wz, double *St, hipStream_t s);
+hipError_t launch_s_export(int64_t nu, int nr, int nmu, int ldmu, const double *St,
+                           double *S, hipStream_t s);
+
+// Step d: unique third moments T[i<=j<=k] = Sum_z St_i St_j St_k.
+struct TriplePlan {
+    int U = 0;                 // number of S rows (na * np)
+    int Upad = 0;              // rows padded to the row super-block
+    int64_t npairs = 0;        // U (U + 1) / 2
+    int ntiles = 0;            // 16-pair column tiles
+    int ngroups = 0;
+    int ntasks = 0;
+    int64_t tsize = 0;         // doubles in the tile-packed T
+    // device arrays
+    int *tile_maxj = nullptr;  // [ntiles]
+    int64_t *tile_off = nullptr; // [ntiles] offset in 16x16 blocks
+    int *group_tile0 = nullptr;  // [ngroups + 1]
+    int *group_rows = nullptr;   // [ngroups][kGroupRows]
+    int *group_nrows = nullptr;  // [ngroups]
+    unsigned short *pair_lj = nullptr; // [ntiles * 16] local row of j in its group
+    unsigned short *pair_lk = nullptr; // [ntiles * 16]
+    int2 *tasks = nullptr;       // [ntasks] (group, row super-block)
+};
+constexpr int kPairsPerGroup = 128;
+constexpr int kGroupRows = 160;
+constexpr int kRowBlock = 128;
+hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err);
+void free_triple_plan(TriplePlan &plan);
+
+hipError_t launch_triple_f64(const TriplePlan &plan, int64_t ldz, int64_t nz,
+                             const double *St, double *T, hipStream_t s);
+// Mixed: St32 is FP32 (for the generated operand) and Sh/Sl the BF16 split
+// (hi, lo) of the same values; z chunks of kMuPad belong to one r each
+// (nmu_pad values per r).
+hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t ldz, int nr, int nmu_pad,
+                               const float *St32, const uint16_t *Sh, const uint16_t *Sl,
+                               double *T, hipStream_t s);
+hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *Sh,
+                             uint16_t *Sl, hipStream_t s);
+
+// Gather Gamma entries from T.
+hipError_t launch_gather(int kind, int ta, int tp, const int *tri_a, const int *tri_p,
+                         int np, const TriplePlan &plan, const double *T, double *gamma,
+                         hipStream_t s);
+
+}  // namespace mp

@@ -1,0 +1,259 @@
+// Steps b and c: the k contraction (beta) and the l contraction (S) as FP64
+// matrix-core GEMMs (v_mfma_f64_16x16x4f64), 64x64 output tiles per
+// 256-thread workgroup, 16-deep K tiles staged through LDS with the next
+// tile prefetched into registers while the current one is multiplied.
+//
+// Step b (Appendix, projected modes; times 2/pi), one GEMM per l:
+//   beta_p(l, r) = Sum_k [Delta_l(k) j_l(k r)] * [(2/pi) wk k^2 q_p(k)]
+//   rows r, columns p, depth k.  The first factor comes from the Bessel
+//   emit pass (already multiplied by Delta_l(k)); the second is formed on
+//   load.
+// Step c (Sec. 2.2, Eq. (legendre)), one GEMM per pair u = (a, p):
+//   S_ap(r, mu) = Sum_l [w_l qbar_a(l) beta_p(l, r)] * P_l(mu)
+//   rows r, columns mu, depth l; the first factor is formed on load.  The
+//   epilogue optionally multiplies by the cube root of the quadrature weight
+//   W(r, mu) = wr r^2 wmu, so that the triple product of three scaled rows
+//   carries W once.
+#include "internal.hpp"
+
+namespace mp {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int LDA = BM + 1, LDB = BN + 1;
+
+// Op interface:
+//   static constexpr bool a_k_fast, b_k_fast;   // which index is contiguous in memory
+//   int M, N, K;
+//   double a(int b, int m, int k) const;   double bv(int b, int k, int n) const;
+//   void store(int b, int m, int n, double v) const;
+template <class Op>
+__global__ __launch_bounds__(256) void k_gemm64(Op op)
+{
+    __shared__ double As[BK][LDA];
+    __shared__ double Bs[BK][LDB];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int b = blockIdx.z;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int M = op.M, N = op.N, K = op.K;
+
+    double ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int m, k;
+            if (Op::a_k_fast) { k = t % BK; m = t / BK + 16 * i; }
+            else              { m = t % BM; k = t / BM + 4 * i; }
+            const int gm = m0 + m, gk = k0 + k;
+            ra[i] = (gm < M && gk < K) ? op.a(b, gm, gk) : 0.0;
+            int n, kk;
+            if (Op::b_k_fast) { kk = t % BK; n = t / BK + 16 * i; }
+            else              { n = t % BN; kk = t / BN + 4 * i; }
+            const int gn = n0 + n, gk2 = k0 + kk;
+            rb[i] = (gn < N && gk2 < K) ? op.bv(b, gk2, gn) : 0.0;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int m, k;
+            if (Op::a_k_fast) { k = t % BK; m = t / BK + 16 * i; }
+            else              { m = t % BM; k = t / BM + 4 * i; }
+            As[k][m] = ra[i];
+            int n, kk;
+            if (Op::b_k_fast) { kk = t % BK; n = t / BK + 16 * i; }
+            else              { n = t % BN; kk = t / BN + 4 * i; }
+            Bs[kk][n] = rb[i];
+        }
+    };
+
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int ktiles = (K + BK - 1) / BK;
+    load(0);
+    for (int kt = 0; kt < ktiles; ++kt) {
+        __syncthreads();
+        stash();
+        __syncthreads();
+        if (kt + 1 < ktiles) load((kt + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = As[kr][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = Bs[kr][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = m0 + wm * 32 + i * 16 + 4 * q + (lane >> 4);
+                const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (m < M && n < N) op.store(b, m, n, acc[i][j][q]);
+            }
+}
+
+// ---- step b ----------------------------------------------------------------
+struct BetaOp {
+    static constexpr bool a_k_fast = true;    // Jd[l][r][k]
+    static constexpr bool b_k_fast = true;    // qk[p][k]
+    int M, N, K;                              // nr, np, nk
+    int l0, lmin, L;
+    const double *Jd, *k, *wk, *qk;
+    double *beta;
+    __device__ double a(int b, int m, int kk) const { return Jd[((size_t)b * M + m) * K + kk]; }
+    __device__ double bv(int, int kk, int n) const
+    {
+        const double kv = k[kk];
+        return (2.0 / kPi) * wk[kk] * kv * kv * qk[(size_t)n * K + kk];
+    }
+    __device__ void store(int b, int m, int n, double v) const
+    {
+        beta[((size_t)n * L + (l0 + b - lmin)) * M + m] = v;
+    }
+};
+
+// ---- step c ----------------------------------------------------------------
+struct SOp {
+    static constexpr bool a_k_fast = false;   // beta[p][l][r]: r contiguous
+    static constexpr bool b_k_fast = false;   // P[l][mu]: mu contiguous
+    int M, N, K;                              // nr, ldmu, L
+    int np, nmu, ldP;
+    const double *wl, *ql, *beta, *P, *wz;
+    double *S;
+    __device__ double a(int u, int m, int l) const
+    {
+        const int ia = u / np, ip = u % np;
+        return wl[l] * ql[(size_t)ia * K + l] * beta[((size_t)ip * K + l) * M + m];
+    }
+    __device__ double bv(int, int l, int n) const { return P[(size_t)l * ldP + n]; }
+    __device__ void store(int u, int m, int n, double v) const
+    {
+        const size_t o = ((size_t)u * M + m) * N + n;
+        if (n >= nmu) { S[o] = 0.0; return; }
+        S[o] = wz ? v * wz[(size_t)m * N + n] : v;
+    }
+};
+
+__global__ void k_weights_l(int L, int lmin, double v_power, const double *__restrict__ cl,
+                            double *__restrict__ wl)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    const double l2 = 2.0 * (lmin + i) + 1.0;
+    wl[i] = pow(l2, 1.0 - v_power) / sqrt(cl[i]);
+}
+
+__global__ void k_cbrt_weights(int nr, int nmu, int ldmu, const double *__restrict__ r,
+                               const double *__restrict__ wr, const double *__restrict__ wmu,
+                               double *__restrict__ wz)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nr * ldmu) return;
+    const int ir = (int)(i / ldmu), im = (int)(i % ldmu);
+    wz[i] = (im < nmu) ? cbrt(wr[ir] * r[ir] * r[ir] * wmu[im]) : 0.0;
+}
+
+__global__ void k_s_import(int64_t nu, int nr, int nmu, int ldmu, const double *__restrict__ S,
+                           const double *__restrict__ wz, double *__restrict__ St)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = nu * nr * ldmu;
+    if (i >= n) return;
+    const int im = (int)(i % ldmu);
+    const int64_t ur = i / ldmu;                  // u * nr + r
+    const int ir = (int)(ur % nr);
+    St[i] = (im < nmu) ? S[ur * nmu + im] * wz[(size_t)ir * ldmu + im] : 0.0;
+}
+
+__global__ void k_s_export(int64_t nu, int nr, int nmu, int ldmu, const double *__restrict__ St,
+                           double *__restrict__ S)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = nu * nr * nmu;
+    if (i >= n) return;
+    const int im = (int)(i % nmu);
+    const int64_t ur = i / nmu;
+    S[i] = St[ur * ldmu + im];
+}
+
+template <class Op>
+hipError_t run(const Op &op, int batches, hipStream_t s)
+{
+    if (op.M <= 0 || op.N <= 0 || batches <= 0) return hipSuccess;
+    dim3 grid((op.M + BM - 1) / BM, (op.N + BN - 1) / BN, batches);
+    hipLaunchKernelGGL(k_gemm64<Op>, grid, dim3(256), 0, s, op);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_beta_gemm(int nl, int l0, int lmin, int L, int nk, int nr, int np,
+                            const double *Jd, const double *k, const double *wk, const double *qk,
+                            double *beta, hipStream_t s)
+{
+    BetaOp op{nr, np, nk, l0, lmin, L, Jd, k, wk, qk, beta};
+    return run(op, nl, s);
+}
+
+hipError_t launch_s_gemm(int na, int np, int nr, int nmu, int ldmu, int L, const double *wl,
+                         const double *ql, const double *beta, const double *P, int ldP,
+                         const double *wz, double *S, hipStream_t s)
+{
+    SOp op{nr, ldmu, L, np, nmu, ldP, wl, ql, beta, P, wz, S};
+    return run(op, na * np, s);
+}
+
+hipError_t launch_weights_l(int L, int lmin, double v_power, const double *cl, double *wl,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_weights_l, dim3((L + 255) / 256), dim3(256), 0, s, L, lmin, v_power, cl, wl);
+    return hipGetLastError();
+}
+
+hipError_t launch_cbrt_weights(int nr, int nmu, int ldmu, const double *r, const double *wr,
+                               const double *wmu, double *wz, hipStream_t s)
+{
+    const int64_t n = (int64_t)nr * ldmu;
+    hipLaunchKernelGGL(k_cbrt_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nr, nmu,
+                       ldmu, r, wr, wmu, wz);
+    return hipGetLastError();
+}
+
+hipError_t launch_s_import(int64_t nu, int nr, int nmu, int ldmu, const double *S, const double *wz,
+                           double *St, hipStream_t s)
+{
+    const int64_t n = nu * nr * ldmu;
+    hipLaunchKernelGGL(k_s_import, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nu, nr, nmu,
+                       ldmu, S, wz, St);
+    return hipGetLastError();
+}
+
+hipError_t launch_s_export(int64_t nu, int nr, int nmu, int ldmu, const double *St, double *S,
+                           hipStream_t s)
+{
+    const int64_t n = nu * nr * nmu;
+    hipLaunchKernelGGL(k_s_export, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nu, nr, nmu,
+                       ldmu, St, S);
+    return hipGetLastError();
+}
+
+}  // namespace mp

@@ -1,0 +1,383 @@
+// Step d: the triple-product quadrature of Eq. (2D).
+//
+// With the S rows pre-scaled by the cube root of the quadrature weight
+// (St_u(z) = W(z)^(1/3) S_u(z), z = (r, mu), u = (a, p)), every entry of the
+// ordered and the symmetric Gamma is built from the third moments
+//
+//     T[u1, u2, u3] = Sum_z St_u1(z) St_u2(z) St_u3(z),
+//
+// a tensor symmetric in (u1, u2, u3): the ordered Gamma entry for
+// (a1 a2 a3),(p1 p2 p3) is T at u_s = (a_s, p_s) over 8 pi, and the
+// symmetric entry is the sum of the six T values of the permanent over
+// 48 pi.  Only the unique entries i <= j <= k are computed (one sixth of the
+// dense work); a gather kernel then assembles Gamma.
+//
+// The unique entries form a matrix product over z: rows i, columns the pairs
+// (j <= k), and the column operand St_j(z) St_k(z) generated on the fly.
+// Pairs are listed by (j, k); 16 consecutive pairs make a column tile, and a
+// 16-row block i0..i0+15 is needed for a tile only when i0 <= max j of the
+// tile.  Tiles are packed T[tile][row block][16][16].
+//
+// Workgroup task = (group of <= 8 column tiles whose pairs touch <= 160
+// distinct rows, 128-row block).  Per 16-wide z chunk the workgroup stages the
+// 128 A rows and the group's rows in LDS (double-buffered, the next chunk
+// prefetched into registers), and each of its four waves owns 64 rows x 64
+// pairs = 4 x 4 matrix-core tiles.  z runs over the whole range inside one
+// workgroup: no split-K, deterministic results.
+//
+// FP64 path: v_mfma_f64_16x16x4f64, FP64 accumulation.
+// Mixed path: see k_triple_mixed below.
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace mp {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int ZC = 16;                       // z values per staged chunk (FP64)
+constexpr int LDSA = kRowBlock + 1;          // padded LDS row lengths (doubles)
+constexpr int LDSG = kGroupRows + 1;
+
+__device__ __forceinline__ int task_of_block(int bid, int ntasks)
+{
+    // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
+    // contiguous run of tasks so neighbouring tasks (which share S rows)
+    // share an L2.
+    const int x = bid & 7, idx = bid >> 3;
+    const int base = ntasks >> 3, rem = ntasks & 7;
+    return x * base + (x < rem ? x : rem) + idx;
+}
+
+struct TripleArgs {
+    const int *tile_maxj;
+    const int64_t *tile_off;
+    const int *group_tile0;
+    const int *group_rows;
+    const int *group_nrows;
+    const unsigned short *pair_lj, *pair_lk;
+    const int2 *tasks;
+    int ntasks;
+    int64_t ldz, nz;
+};
+
+__global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const double *__restrict__ St,
+                                                       double *__restrict__ T)
+{
+    __shared__ double Sa[2][ZC][LDSA];
+    __shared__ double Sg[2][ZC][LDSG];
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int task = task_of_block(blockIdx.x, A.ntasks);
+    const int2 tk = A.tasks[task];
+    const int g = tk.x, rb = tk.y;
+    const int t0 = A.group_tile0[g], nt = A.group_tile0[g + 1] - t0;
+    const int ngr = A.group_nrows[g];
+    const int *grow = A.group_rows + (size_t)g * kGroupRows;
+    const int row0 = rb * kRowBlock;
+
+    // this lane's four pairs (one per column tile of the wave)
+    int lj[4], lk[4];
+    unsigned mask = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int tj = wn * 4 + j;
+        lj[j] = 0;
+        lk[j] = 0;
+        if (tj < nt) {
+            const int q = (t0 + tj) * 16 + (lane & 15);
+            lj[j] = A.pair_lj[q];
+            lk[j] = A.pair_lk[q];
+            const int mj = A.tile_maxj[t0 + tj];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (row0 + wm * 64 + i * 16 <= mj) mask |= 1u << (i * 4 + j);
+        }
+    }
+    mask = __builtin_amdgcn_readfirstlane(mask);
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    // staging: A rows 128 x 16 z = 1024 double2 (4 per thread);
+    // group rows <= 160 x 16 z = 1280 double2 (<= 5 per thread)
+    double2 pa[4], pg[5];
+    auto gload = [&](int64_t z0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = t + 256 * i;
+            const int row = idx >> 3, zp = idx & 7;
+            pa[i] = *reinterpret_cast<const double2 *>(St + (size_t)(row0 + row) * A.ldz + z0 + 2 * zp);
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const int idx = t + 256 * i;
+            const int row = idx >> 3, zp = idx & 7;
+            if (row < ngr)
+                pg[i] = *reinterpret_cast<const double2 *>(St + (size_t)grow[row] * A.ldz + z0 + 2 * zp);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = t + 256 * i;
+            const int row = idx >> 3, zp = idx & 7;
+            Sa[buf][2 * zp][row] = pa[i].x;
+            Sa[buf][2 * zp + 1][row] = pa[i].y;
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const int idx = t + 256 * i;
+            const int row = idx >> 3, zp = idx & 7;
+            if (row < ngr) {
+                Sg[buf][2 * zp][row] = pg[i].x;
+                Sg[buf][2 * zp + 1][row] = pg[i].y;
+            }
+        }
+    };
+
+    const int64_t nchunks = A.nz / ZC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const int buf = (int)(c & 1);
+        if (c + 1 < nchunks) gload((c + 1) * ZC);
+#pragma unroll
+        for (int ks = 0; ks < ZC / 4; ++ks) {
+            const int z = ks * 4 + (lane >> 4);
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = Sa[buf][z][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Sg[buf][z][lj[j]] * Sg[buf][z][lk[j]];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (mask & (1u << (i * 4 + j)))
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        if (c + 1 < nchunks) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!(mask & (1u << (i * 4 + j)))) continue;
+            const int tile = t0 + wn * 4 + j;
+            const int blk = (row0 + wm * 64 + i * 16) >> 4;
+            double *dst = T + ((size_t)(A.tile_off[tile] + blk) << 8);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[(4 * q + (lane >> 4)) * 16 + (lane & 15)] = acc[i][j][q];
+        }
+}
+
+// ---- gather ---------------------------------------------------------------
+__device__ __forceinline__ double tget(int a, int b, int c, int U, const int64_t *__restrict__ toff,
+                                       const double *__restrict__ T)
+{
+    // sort a <= b <= c
+    int lo = min(a, min(b, c)), hi = max(a, max(b, c));
+    int mid = a + b + c - lo - hi;
+    const int64_t q = (int64_t)mid * U - (int64_t)mid * (mid - 1) / 2 + (hi - mid);
+    const int64_t tile = q >> 4;
+    const int n = (int)(q & 15);
+    return T[((size_t)(toff[tile] + (lo >> 4)) << 8) + ((lo & 15) << 4) + n];
+}
+
+__global__ void k_gather(int kind, int ta, int tp, const int *__restrict__ tri_a,
+                         const int *__restrict__ tri_p, int np, int U,
+                         const int64_t *__restrict__ toff, const double *__restrict__ T,
+                         double *__restrict__ gamma)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)ta * tp) return;
+    const int n = (int)(e / tp), m = (int)(e % tp);
+    const int a0 = tri_a[3 * n] * np, a1 = tri_a[3 * n + 1] * np, a2 = tri_a[3 * n + 2] * np;
+    const int p0 = tri_p[3 * m], p1 = tri_p[3 * m + 1], p2 = tri_p[3 * m + 2];
+    double v;
+    if (kind == MODAL_GAMMA_ORDERED) {
+        v = tget(a0 + p0, a1 + p1, a2 + p2, U, toff, T) * (1.0 / (8.0 * kPi));
+    } else {
+        v = tget(a0 + p0, a1 + p1, a2 + p2, U, toff, T) + tget(a0 + p0, a1 + p2, a2 + p1, U, toff, T)
+          + tget(a0 + p1, a1 + p0, a2 + p2, U, toff, T) + tget(a0 + p1, a1 + p2, a2 + p0, U, toff, T)
+          + tget(a0 + p2, a1 + p0, a2 + p1, U, toff, T) + tget(a0 + p2, a1 + p1, a2 + p0, U, toff, T);
+        v *= 1.0 / (48.0 * kPi);
+    }
+    gamma[e] = v;
+}
+
+}  // namespace
+
+// ---- plan -----------------------------------------------------------------
+hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err)
+{
+    free_triple_plan(plan);
+    plan.U = U;
+    plan.Upad = pad_to(U, kRowBlock);
+    plan.npairs = (int64_t)U * (U + 1) / 2;
+    plan.ntiles = (int)((plan.npairs + 15) / 16);
+    const int nt = plan.ntiles;
+    std::vector<int> pj((size_t)nt * 16, 0), pk((size_t)nt * 16, 0);
+    {
+        int64_t q = 0;
+        for (int j = 0; j < U; ++j)
+            for (int k = j; k < U; ++k, ++q) {
+                pj[q] = j;
+                pk[q] = k;
+            }
+        for (; q < (int64_t)nt * 16; ++q) { pj[q] = 0; pk[q] = 0; }   // padding pairs
+    }
+    std::vector<int> maxj(nt);
+    std::vector<int64_t> toff(nt);
+    int64_t acc = 0;
+    for (int t = 0; t < nt; ++t) {
+        int64_t last = std::min<int64_t>((int64_t)t * 16 + 15, plan.npairs - 1);
+        maxj[t] = pj[last];
+        toff[t] = acc;
+        acc += maxj[t] / 16 + 1;
+    }
+    plan.tsize = acc * 256;
+
+    // groups of <= 8 tiles touching <= kGroupRows distinct rows
+    std::vector<int> gt0;
+    std::vector<int> grows;
+    std::vector<int> gn;
+    std::vector<unsigned short> lj((size_t)nt * 16), lk((size_t)nt * 16);
+    std::vector<int> stamp(U, -1), local(U, 0);
+    int t = 0;
+    while (t < nt) {
+        const int g = (int)gt0.size();
+        gt0.push_back(t);
+        std::vector<int> rows;
+        int ntg = 0;
+        while (t < nt && ntg < kPairsPerGroup / 16) {
+            int add = 0;
+            int seen[32];
+            int ns = 0;
+            for (int e = 0; e < 16; ++e) {
+                for (int v : {pj[(size_t)t * 16 + e], pk[(size_t)t * 16 + e]}) {
+                    if (stamp[v] == g) continue;
+                    bool dup = false;
+                    for (int s = 0; s < ns; ++s) dup |= (seen[s] == v);
+                    if (!dup) { seen[ns++] = v; ++add; }
+                }
+            }
+            if ((int)rows.size() + add > kGroupRows) break;
+            for (int s = 0; s < ns; ++s) {
+                stamp[seen[s]] = g;
+                local[seen[s]] = (int)rows.size();
+                rows.push_back(seen[s]);
+            }
+            for (int e = 0; e < 16; ++e) {
+                lj[(size_t)t * 16 + e] = (unsigned short)local[pj[(size_t)t * 16 + e]];
+                lk[(size_t)t * 16 + e] = (unsigned short)local[pk[(size_t)t * 16 + e]];
+            }
+            ++t;
+            ++ntg;
+        }
+        gn.push_back((int)rows.size());
+        rows.resize(kGroupRows, 0);
+        grows.insert(grows.end(), rows.begin(), rows.end());
+    }
+    plan.ngroups = (int)gt0.size();
+    gt0.push_back(nt);
+    std::vector<int2> tasks;
+    for (int g = 0; g < plan.ngroups; ++g) {
+        int mj = 0;
+        for (int tt = gt0[g]; tt < gt0[g + 1]; ++tt) mj = std::max(mj, maxj[tt]);
+        for (int rb = 0; rb <= mj / kRowBlock; ++rb) tasks.push_back(make_int2(g, rb));
+    }
+    plan.ntasks = (int)tasks.size();
+
+    hipError_t e = hipSuccess;
+    auto up = [&](auto *&dst, const auto &src) {
+        using T = std::remove_reference_t<decltype(src[0])>;
+        if (e != hipSuccess) return;
+        e = hipMalloc((void **)&dst, sizeof(T) * std::max<size_t>(src.size(), 1));
+        if (e == hipSuccess && !src.empty())
+            e = hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    };
+    up(plan.tile_maxj, maxj);
+    up(plan.tile_off, toff);
+    up(plan.group_tile0, gt0);
+    up(plan.group_rows, grows);
+    up(plan.group_nrows, gn);
+    up(plan.pair_lj, lj);
+    up(plan.pair_lk, lk);
+    up(plan.tasks, tasks);
+    if (e != hipSuccess) {
+        err = std::string("triple plan upload: ") + hipGetErrorString(e);
+        free_triple_plan(plan);
+    }
+    return e;
+}
+
+void free_triple_plan(TriplePlan &p)
+{
+    (void)hipFree(p.tile_maxj);
+    (void)hipFree(p.tile_off);
+    (void)hipFree(p.group_tile0);
+    (void)hipFree(p.group_rows);
+    (void)hipFree(p.group_nrows);
+    (void)hipFree(p.pair_lj);
+    (void)hipFree(p.pair_lk);
+    (void)hipFree(p.tasks);
+    p = TriplePlan{};
+}
+
+static TripleArgs args_of(const TriplePlan &p, int64_t ldz, int64_t nz)
+{
+    TripleArgs a;
+    a.tile_maxj = p.tile_maxj;
+    a.tile_off = p.tile_off;
+    a.group_tile0 = p.group_tile0;
+    a.group_rows = p.group_rows;
+    a.group_nrows = p.group_nrows;
+    a.pair_lj = p.pair_lj;
+    a.pair_lk = p.pair_lk;
+    a.tasks = p.tasks;
+    a.ntasks = p.ntasks;
+    a.ldz = ldz;
+    a.nz = nz;
+    return a;
+}
+
+hipError_t launch_triple_f64(const TriplePlan &plan, int64_t ldz, int64_t nz, const double *St,
+                             double *T, hipStream_t s)
+{
+    if (nz % ZC != 0 || ldz % 2 != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_triple_f64, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, ldz, nz), St, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int kind, int ta, int tp, const int *tri_a, const int *tri_p, int np,
+                         const TriplePlan &plan, const double *T, double *gamma, hipStream_t s)
+{
+    const int64_t n = (int64_t)ta * tp;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kind, ta, tp,
+                       tri_a, tri_p, np, plan.U, plan.tile_off, T, gamma);
+    return hipGetLastError();
+}
+
+hipError_t launch_triple_mixed(const TriplePlan &, int64_t, int, int, const float *, const uint16_t *,
+                               const uint16_t *, double *, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_split_bf16(int64_t, const double *, float *, uint16_t *, uint16_t *, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+}  // namespace mp
