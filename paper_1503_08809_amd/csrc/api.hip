@@ -36,7 +36,7 @@ struct modal_ctx_s {
     Buf ws[NSLOTS];
     size_t limit = 0;
     int next_in = 0;
-    TriplePlan plan;
+    TriplePlan plan64, planmx;         // triple-product plans of the FP64 / mixed kernels
     bool timing = false;
     // per stage: a pool of (start, end) event pairs; the first `used` belong
     // to the last call (chunked stages record one pair per chunk)
@@ -380,42 +380,44 @@ void run_beta(modal_ctx c, const modal_grid *g, const Dims &d, const Grid &G, co
 // rowscale[(l - lrow0) * nk + k] with lrow0 = llo, so the pointer is offset to
 // row llo of delta.
 
-void ensure_plan(modal_ctx c, int U)
+const TriplePlan &ensure_plan(modal_ctx c, int U, modal_precision prec)
 {
-    if (c->plan.U == U && c->plan.tasks) return;
+    TriplePlan &pl = (prec == MODAL_FP64) ? c->plan64 : c->planmx;
+    if (pl.U == U && pl.tasks) return pl;
+    int rb, tpg, gr;
+    if (prec == MODAL_FP64) triple_f64_shape(rb, tpg, gr);
+    else triple_mixed_shape(rb, tpg, gr);
     std::string err;
     hipck(c, hipStreamSynchronize(c->stream), "sync");
-    hipError_t e = build_triple_plan(U, c->plan, err);
+    hipError_t e = build_triple_plan(U, rb, tpg, gr, pl, err);
     if (e != hipSuccess) fail(c, e == hipErrorOutOfMemory ? MODAL_ERR_OOM : MODAL_ERR_DEVICE, err);
+    return pl;
 }
 
 // Triple products from scaled rows St ([Upad][nr * ldmu]) and gather.
 void run_triple_gather(modal_ctx c, const modal_problem *p, const Dims &d, modal_precision prec,
                        double *St, double *gamma)
 {
-    ensure_plan(c, d.U);
+    const TriplePlan &plan = ensure_plan(c, d.U, prec);
     const int64_t ldz = (int64_t)d.nr * d.ldmu;
-    double *T = (double *)ws_get(c, W_T, sizeof(double) * (size_t)c->plan.tsize);
+    double *T = (double *)ws_get(c, W_T, sizeof(double) * (size_t)plan.tsize);
     {
         StageTimer tm(c, MODAL_STAGE_TRIPLE);
         if (prec == MODAL_FP64) {
-            hipck(c, launch_triple_f64(c->plan, ldz, ldz, St, T, c->stream), "triple f64");
+            hipck(c, launch_triple_f64(plan, ldz, ldz, St, T, c->stream), "triple f64");
         } else {
-            const size_t n = (size_t)c->plan.Upad * ldz;
+            const size_t n = (size_t)pad_to(d.U, kRowPad) * ldz;
             float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * n);
-            uint16_t *sh = (uint16_t *)ws_get(c, W_SH, sizeof(uint16_t) * n);
-            uint16_t *sl = (uint16_t *)ws_get(c, W_SL, sizeof(uint16_t) * n);
-            hipError_t e = launch_split_bf16((int64_t)n, St, s32, sh, sl, c->stream);
-            if (e == hipErrorNotSupported) fail(c, MODAL_ERR_UNSUPPORTED, "mixed precision not built");
-            hipck(c, e, "split");
-            hipck(c, launch_triple_mixed(c->plan, ldz, d.nr, d.ldmu, s32, sh, sl, T, c->stream), "triple mixed");
+            uint16_t *sa = (uint16_t *)ws_get(c, W_SH, 2 * sizeof(uint16_t) * n);
+            hipck(c, launch_split_bf16(pad_to(d.U, kRowPad), ldz, St, s32, sa, c->stream), "split");
+            hipck(c, launch_triple_mixed(plan, ldz, d.nr, d.ldmu, s32, sa, T, c->stream), "triple mixed");
         }
     }
     const int *ta = dev_in(c, p->tri_a, (size_t)p->ta * 3);
     const int *tp = dev_in(c, p->tri_p, (size_t)p->tp * 3);
     if ((int64_t)p->ta * p->tp == 0) return;
     StageTimer tm(c, MODAL_STAGE_GATHER);
-    hipck(c, launch_gather(p->kind, p->ta, p->tp, ta, tp, d.np, c->plan, T, gamma, c->stream), "gather");
+    hipck(c, launch_gather(p->kind, p->ta, p->tp, ta, tp, d.np, plan, T, gamma, c->stream), "gather");
 }
 
 }  // namespace
@@ -463,7 +465,8 @@ modal_status modal_destroy(modal_ctx c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto &b : c->ws) (void)hipFree(b.p);
-    free_triple_plan(c->plan);
+    free_triple_plan(c->plan64);
+    free_triple_plan(c->planmx);
     for (auto &pool : c->ev)
         for (auto &pr : pool) {
             (void)hipEventDestroy(pr.first);
@@ -547,7 +550,7 @@ modal_status modal_workspace_bytes(modal_ctx c, const modal_grid *g, const modal
         check_prec(c, prec);
         Dims d = check_grid(c, g, false);
         check_problem(c, p, d, true, false);
-        const size_t Upad = (size_t)pad_to(d.U, kRowBlock);
+        const size_t Upad = (size_t)pad_to(d.U, kRowPad);
         const size_t z = (size_t)d.nr * d.ldmu;
         const size_t nitems = (size_t)d.nk * d.nr;
         size_t cl = std::max<size_t>(1, std::min<size_t>((size_t)d.L, ((size_t)512 << 20) / (nitems * 8)));
@@ -557,7 +560,7 @@ modal_status modal_workspace_bytes(modal_ctx c, const modal_grid *g, const modal
         b += 2 * d.nmu * 8 + (size_t)d.L * d.ldmu * 8 + d.L * 8 + z * 8;
         b += nitems * 40 + cl * nitems * 8 + (size_t)d.np * d.L * d.nr * 8;
         b += Upad * z * 8 + tsize * 8;
-        if (prec == MODAL_MIXED) b += Upad * z * 8;
+        if (prec == MODAL_MIXED) b += Upad * z * 8;   // FP32 copy + BF16 split
         *bytes = b;
     });
 }
@@ -673,7 +676,7 @@ modal_status modal_gamma_from_S(modal_ctx c, const modal_grid *g, const modal_pr
         need(c, gamma != nullptr || (int64_t)p->ta * p->tp == 0, MODAL_ERR_INVALID_ARG, "gamma is NULL");
         Grid G = stage_grid(c, g, d);
         const double *dS = dev_in(c, S, (size_t)d.U * d.nr * d.nmu);
-        const int Upad = pad_to(d.U, kRowBlock);
+        const int Upad = pad_to(d.U, kRowPad);
         const int64_t ldz = (int64_t)d.nr * d.ldmu;
         double *wz = (double *)ws_get(c, W_WZ, sizeof(double) * ldz);
         double *St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * ldz);
@@ -717,7 +720,7 @@ modal_status modal_gamma(modal_ctx c, const modal_grid *g, const modal_problem *
         double *beta = (double *)ws_get(c, W_BETA, sizeof(double) * (size_t)d.np * d.L * d.nr);
         run_beta(c, g, d, G, delta, qk, beta);
         // (c) the l contraction, scaled rows
-        const int Upad = pad_to(d.U, kRowBlock);
+        const int Upad = pad_to(d.U, kRowPad);
         double *St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * ldz);
         {
             StageTimer tm(c, MODAL_STAGE_S);

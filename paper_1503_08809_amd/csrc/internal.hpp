@@ -71,9 +71,13 @@ hipError_t launch_s_export(int64_t nu, int nr, int nmu, int ldmu, const double *
                            double *S, hipStream_t s);
 
 // Step d: unique third moments T[i<=j<=k] = Sum_z St_i St_j St_k.
+// A plan lists the 16-pair column tiles, their packing offsets in T (shared
+// by every plan of the same U), and the workgroup tasks of one kernel shape:
+// groups of `tiles_per_group` column tiles touching at most `group_rows`
+// distinct rows, times row super-blocks of `rowblock` rows.
 struct TriplePlan {
     int U = 0;                 // number of S rows (na * np)
-    int Upad = 0;              // rows padded to the row super-block
+    int rowblock = 0, tiles_per_group = 0, group_rows = 0;
     int64_t npairs = 0;        // U (U + 1) / 2
     int ntiles = 0;            // 16-pair column tiles
     int ngroups = 0;
@@ -83,28 +87,30 @@ struct TriplePlan {
     int *tile_maxj = nullptr;  // [ntiles]
     int64_t *tile_off = nullptr; // [ntiles] offset in 16x16 blocks
     int *group_tile0 = nullptr;  // [ngroups + 1]
-    int *group_rows = nullptr;   // [ngroups][kGroupRows]
+    int *group_rows_idx = nullptr; // [ngroups][group_rows]
     int *group_nrows = nullptr;  // [ngroups]
     unsigned short *pair_lj = nullptr; // [ntiles * 16] local row of j in its group
     unsigned short *pair_lk = nullptr; // [ntiles * 16]
     int2 *tasks = nullptr;       // [ntasks] (group, row super-block)
 };
-constexpr int kPairsPerGroup = 128;
-constexpr int kGroupRows = 160;
-constexpr int kRowBlock = 128;
-hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err);
+// S rows are allocated padded to a multiple of kRowPad (>= every rowblock).
+constexpr int kRowPad = 256;
+hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group_rows,
+                             TriplePlan &plan, std::string &err);
 void free_triple_plan(TriplePlan &plan);
+// shapes of the two kernels
+void triple_f64_shape(int &rowblock, int &tiles_per_group, int &group_rows);
+void triple_mixed_shape(int &rowblock, int &tiles_per_group, int &group_rows);
 
 hipError_t launch_triple_f64(const TriplePlan &plan, int64_t ldz, int64_t nz,
                              const double *St, double *T, hipStream_t s);
-// Mixed: St32 is FP32 (for the generated operand) and Sh/Sl the BF16 split
-// (hi, lo) of the same values; z chunks of kMuPad belong to one r each
-// (nmu_pad values per r).
+// Mixed: S32 is the FP32 copy of the scaled rows (sources of the generated
+// operand) and SA the BF16 (hi, lo) split packed per 8 z values
+// ([row][z/8][8 hi, 8 lo]); each r holds nmu_pad z values (a multiple of 32).
 hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t ldz, int nr, int nmu_pad,
-                               const float *St32, const uint16_t *Sh, const uint16_t *Sl,
-                               double *T, hipStream_t s);
-hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *Sh,
-                             uint16_t *Sl, hipStream_t s);
+                               const float *S32, const uint16_t *SA, double *T, hipStream_t s);
+hipError_t launch_split_bf16(int64_t nrows, int64_t ldz, const double *St, float *S32,
+                             uint16_t *SA, hipStream_t s);
 
 // Gather Gamma entries from T.
 hipError_t launch_gather(int kind, int ta, int tp, const int *tri_a, const int *tri_p,

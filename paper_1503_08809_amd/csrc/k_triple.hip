@@ -18,28 +18,47 @@
 // 16-row block i0..i0+15 is needed for a tile only when i0 <= max j of the
 // tile.  Tiles are packed T[tile][row block][16][16].
 //
-// Workgroup task = (group of <= 8 column tiles whose pairs touch <= 160
-// distinct rows, 128-row block).  Per 16-wide z chunk the workgroup stages the
-// 128 A rows and the group's rows in LDS (double-buffered, the next chunk
-// prefetched into registers), and each of its four waves owns 64 rows x 64
-// pairs = 4 x 4 matrix-core tiles.  z runs over the whole range inside one
-// workgroup: no split-K, deterministic results.
+// A workgroup task is (group of column tiles whose pairs touch a bounded set
+// of distinct rows, row super-block).  z runs over the whole range inside one
+// workgroup: no split-K, no atomics, deterministic results.
 //
-// FP64 path: v_mfma_f64_16x16x4f64, FP64 accumulation.
-// Mixed path: see k_triple_mixed below.
+// FP64 path (k_triple_f64): v_mfma_f64_16x16x4f64.  Tasks are 8 column tiles
+// x 128 rows; per 16-wide z chunk the workgroup stages the 128 A rows and
+// the group's rows in LDS (double-buffered, next chunk prefetched into
+// registers); each of the four waves owns 64 rows x 64 pairs.
+//
+// Mixed path (k_triple_mixed): v_mfma_f32_16x16x32_bf16 on a split of both
+// operands into high and low BF16 parts, x = x_hi + x_lo, keeping the three
+// products hi*hi + hi*lo + lo*hi of each term (the dropped lo*lo is ~2^-16
+// of the term).  Tasks are 4 column tiles x 256 rows; each wave owns 64 rows
+// and all 64 pairs, loads its A fragments (pre-split rows) straight from
+// memory, and generates one column tile of the product operand per 32-wide
+// z step (FP32 product of two FP32 rows, then split), shared with the other
+// waves through LDS.  Each r's mu sum is accumulated in FP32 by the matrix
+// cores; the per-r sums are added in FP32 for blocks of kRBlock radial
+// points, and the blocks are accumulated in FP64 in T.  The mu sum of an r is
+// always complete before it enters the r sum (Sec. 2.2).
 #include "internal.hpp"
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 namespace mp {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// ---- shapes -----------------------------------------------------------------
+constexpr int F64_ROWBLOCK = 128, F64_TILES = 8, F64_GROUP_ROWS = 160;
+constexpr int MX_ROWBLOCK = 256, MX_TILES = 4, MX_GROUP_ROWS = 96;
+constexpr int kRBlock = 16;                  // radial points per FP32 block (mixed)
 
 constexpr int ZC = 16;                       // z values per staged chunk (FP64)
-constexpr int LDSA = kRowBlock + 1;          // padded LDS row lengths (doubles)
-constexpr int LDSG = kGroupRows + 1;
+constexpr int LDSA = F64_ROWBLOCK + 1;       // padded LDS row lengths (doubles)
+constexpr int LDSG = F64_GROUP_ROWS + 1;
 
 __device__ __forceinline__ int task_of_block(int bid, int ntasks)
 {
@@ -60,9 +79,13 @@ struct TripleArgs {
     const unsigned short *pair_lj, *pair_lk;
     const int2 *tasks;
     int ntasks;
+    int group_cap;
     int64_t ldz, nz;
 };
 
+// ============================================================================
+// FP64
+// ============================================================================
 __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const double *__restrict__ St,
                                                        double *__restrict__ T)
 {
@@ -76,8 +99,8 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
     const int g = tk.x, rb = tk.y;
     const int t0 = A.group_tile0[g], nt = A.group_tile0[g + 1] - t0;
     const int ngr = A.group_nrows[g];
-    const int *grow = A.group_rows + (size_t)g * kGroupRows;
-    const int row0 = rb * kRowBlock;
+    const int *grow = A.group_rows + (size_t)g * A.group_cap;
+    const int row0 = rb * F64_ROWBLOCK;
 
     // this lane's four pairs (one per column tile of the wave)
     int lj[4], lk[4];
@@ -168,6 +191,7 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
         __syncthreads();
     }
 
+    // FP64 16x16x4 result layout: lane l, element q -> row 4q + l/16, column l%16
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -179,6 +203,245 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
 #pragma unroll
             for (int q = 0; q < 4; ++q) dst[(4 * q + (lane >> 4)) * 16 + (lane & 15)] = acc[i][j][q];
         }
+}
+
+// ============================================================================
+// Mixed: split BF16 on matrix cores
+// ============================================================================
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// one operand fragment: 8 BF16 high parts and 8 low parts
+struct Frag {
+    uint4 hi, lo;
+};
+
+__device__ __forceinline__ bf8 as_bf8(uint4 v)
+{
+    bf8 r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+
+// split 8 FP32 values into BF16 high parts (round to nearest even) and the
+// BF16 rounding of the exact remainders
+__device__ __forceinline__ Frag split8(const float v[8])
+{
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t h0 = bf16_rne_bits(v[2 * i]), h1 = bf16_rne_bits(v[2 * i + 1]);
+        const float r0 = v[2 * i] - __uint_as_float(h0 << 16);
+        const float r1 = v[2 * i + 1] - __uint_as_float(h1 << 16);
+        h[i] = h0 | (h1 << 16);
+        l[i] = bf16_rne_bits(r0) | (bf16_rne_bits(r1) << 16);
+    }
+    Frag f;
+    f.hi = make_uint4(h[0], h[1], h[2], h[3]);
+    f.lo = make_uint4(l[0], l[1], l[2], l[3]);
+    return f;
+}
+
+constexpr int MX_KZ = 32;                    // z values per matrix-core step
+constexpr int MX_SRC_LD = MX_KZ + 4;         // padded LDS row (floats)
+
+__global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int kpr,
+                                                      const float *__restrict__ S32,
+                                                      const uint16_t *__restrict__ SA,
+                                                      double *__restrict__ T)
+{
+    constexpr int CT = MX_TILES;
+    __shared__ float Src[2][MX_GROUP_ROWS][MX_SRC_LD];
+    __shared__ uint4 Bb[2][CT][2][64];               // [buf][tile][hi/lo][lane]
+
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int task = task_of_block(blockIdx.x, A.ntasks);
+    const int2 tk = A.tasks[task];
+    const int g = tk.x, rb = tk.y;
+    const int t0 = A.group_tile0[g], nt = A.group_tile0[g + 1] - t0;
+    const int ngr = A.group_nrows[g];
+    const int *grow = A.group_rows + (size_t)g * A.group_cap;
+    const int row0 = rb * MX_ROWBLOCK + wave * 64;   // this wave's 64 rows
+    const int n = lane & 15, zg = lane >> 4;
+
+    // the column tile this wave generates (tile index == wave)
+    const bool gen = wave < nt;
+    int gj = 0, gk = 0;
+    if (gen) {
+        const int q = (t0 + wave) * 16 + n;
+        gj = A.pair_lj[q];
+        gk = A.pair_lk[q];
+    }
+    unsigned mask = 0;
+    for (int j = 0; j < CT; ++j) {
+        if (j >= nt) break;
+        const int mj = A.tile_maxj[t0 + j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (row0 + i * 16 <= mj) mask |= 1u << (i * CT + j);
+    }
+    mask = __builtin_amdgcn_readfirstlane(mask);
+
+    f4 acc[4][CT], tot[4][CT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+            tot[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+
+    const int64_t ldzb = A.ldz / 8;                  // 8-z blocks per row
+    const int64_t nsteps = A.nz / MX_KZ;
+    // A fragments: row row0 + 16 i + n, z block 4 s + zg
+    auto aload = [&](int64_t s, Frag (&f)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(
+                SA + (((size_t)(row0 + 16 * i + n) * ldzb + 4 * s + zg) << 4));
+            f[i].hi = p[0];
+            f[i].lo = p[1];
+        }
+    };
+    // source rows of the group: ngr x 32 floats = ngr x 8 float4 (<= 3 per thread)
+    constexpr int SRC_PER = (MX_GROUP_ROWS * 8 + 255) / 256;
+    float4 sreg[SRC_PER];
+    auto sload = [&](int64_t s) {
+#pragma unroll
+        for (int i = 0; i < SRC_PER; ++i) {
+            const int idx = t + 256 * i;
+            const int row = idx >> 3, q = idx & 7;
+            if (row < ngr)
+                sreg[i] = *reinterpret_cast<const float4 *>(S32 + (size_t)grow[row] * A.ldz + s * MX_KZ + 4 * q);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < SRC_PER; ++i) {
+            const int idx = t + 256 * i;
+            const int row = idx >> 3, q = idx & 7;
+            if (row < ngr) *reinterpret_cast<float4 *>(&Src[buf][row][4 * q]) = sreg[i];
+        }
+    };
+    auto bgen = [&](int buf) {
+        if (!gen) return;
+        float v[8];
+        const float *pj = &Src[buf][gj][8 * zg];
+        const float *pk = &Src[buf][gk][8 * zg];
+        const float4 j0 = *reinterpret_cast<const float4 *>(pj), j1 = *reinterpret_cast<const float4 *>(pj + 4);
+        const float4 k0 = *reinterpret_cast<const float4 *>(pk), k1 = *reinterpret_cast<const float4 *>(pk + 4);
+        v[0] = j0.x * k0.x; v[1] = j0.y * k0.y; v[2] = j0.z * k0.z; v[3] = j0.w * k0.w;
+        v[4] = j1.x * k1.x; v[5] = j1.y * k1.y; v[6] = j1.z * k1.z; v[7] = j1.w * k1.w;
+        const Frag f = split8(v);
+        Bb[buf][wave][0][lane] = f.hi;
+        Bb[buf][wave][1][lane] = f.lo;
+    };
+
+    // prologue: sources of steps 0 and 1 in LDS, operand of step 0 generated
+    Frag acur[4], anext[4];
+    sload(0);
+    sstore(0);
+    if (nsteps > 1) {
+        sload(1);
+        sstore(1);
+    }
+    __syncthreads();
+    bgen(0);
+    if (nsteps > 2) sload(2);
+    aload(0, acur);
+    __syncthreads();
+
+    int rcount = 0;                                  // completed r values
+    int kin = 0;                                     // step within the current r
+    bool first_flush = true;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int buf = (int)(s & 1);
+        if (s + 1 < nsteps) bgen(buf ^ 1);           // operand of step s + 1
+        if (s + 2 < nsteps) sstore(buf);             // sources of step s + 2
+        if (s + 3 < nsteps) sload(s + 3);
+        if (s + 1 < nsteps) aload(s + 1, anext);
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            const bf8 bh = as_bf8(Bb[buf][j][0][lane]);
+            const bf8 bl = as_bf8(Bb[buf][j][1][lane]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (!(mask & (1u << (i * CT + j)))) continue;
+                const bf8 ah = as_bf8(acur[i].hi), al = as_bf8(acur[i].lo);
+                f4 c = acc[i][j];
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+                acc[i][j] = c;
+            }
+        }
+        if (++kin == kpr) {                          // this r's mu sum is complete
+            kin = 0;
+            ++rcount;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < CT; ++j) {
+                    tot[i][j] += acc[i][j];
+                    acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+                }
+            if (rcount % kRBlock == 0 || rcount == nr) {
+                // accumulate the block of r sums in FP64
+                // (BF16 16x16x32 result layout: lane l, element q -> row 4(l/16) + q, column l%16)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < CT; ++j) {
+                        if (!(mask & (1u << (i * CT + j)))) continue;
+                        const int blk = (row0 + i * 16) >> 4;
+                        double *dst = T + ((size_t)(A.tile_off[t0 + j] + blk) << 8);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            double *d = dst + (4 * zg + q) * 16 + n;
+                            const double v = (double)tot[i][j][q];
+                            *d = first_flush ? v : *d + v;
+                        }
+                        tot[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+                    }
+                first_flush = false;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acur[i] = anext[i];
+        __syncthreads();
+    }
+}
+
+__global__ void k_split_bf16(int64_t nrows, int64_t ldz, const double *__restrict__ St,
+                             float *__restrict__ S32, uint16_t *__restrict__ SA)
+{
+    // one thread per 8-z block of a row
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nb = nrows * (ldz / 8);
+    if (i >= nb) return;
+    const double *src = St + i * 8;
+    float f[8];
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = (float)src[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double x0 = src[2 * e], x1 = src[2 * e + 1];
+        const uint32_t h0 = bf16_rne_bits(f[2 * e]), h1 = bf16_rne_bits(f[2 * e + 1]);
+        const float r0 = (float)(x0 - (double)__uint_as_float(h0 << 16));
+        const float r1 = (float)(x1 - (double)__uint_as_float(h1 << 16));
+        h[e] = h0 | (h1 << 16);
+        l[e] = bf16_rne_bits(r0) | (bf16_rne_bits(r1) << 16);
+    }
+    float4 *o32 = reinterpret_cast<float4 *>(S32 + i * 8);
+    o32[0] = make_float4(f[0], f[1], f[2], f[3]);
+    o32[1] = make_float4(f[4], f[5], f[6], f[7]);
+    uint4 *oa = reinterpret_cast<uint4 *>(SA + i * 16);
+    oa[0] = make_uint4(h[0], h[1], h[2], h[3]);
+    oa[1] = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
 // ---- gather ---------------------------------------------------------------
@@ -219,11 +482,28 @@ __global__ void k_gather(int kind, int ta, int tp, const int *__restrict__ tri_a
 }  // namespace
 
 // ---- plan -----------------------------------------------------------------
-hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err)
+void triple_f64_shape(int &rb, int &tpg, int &gr)
+{
+    rb = F64_ROWBLOCK;
+    tpg = F64_TILES;
+    gr = F64_GROUP_ROWS;
+}
+
+void triple_mixed_shape(int &rb, int &tpg, int &gr)
+{
+    rb = MX_ROWBLOCK;
+    tpg = MX_TILES;
+    gr = MX_GROUP_ROWS;
+}
+
+hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group_cap,
+                             TriplePlan &plan, std::string &err)
 {
     free_triple_plan(plan);
     plan.U = U;
-    plan.Upad = pad_to(U, kRowBlock);
+    plan.rowblock = rowblock;
+    plan.tiles_per_group = tiles_per_group;
+    plan.group_rows = group_cap;
     plan.npairs = (int64_t)U * (U + 1) / 2;
     plan.ntiles = (int)((plan.npairs + 15) / 16);
     const int nt = plan.ntiles;
@@ -248,10 +528,8 @@ hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err)
     }
     plan.tsize = acc * 256;
 
-    // groups of <= 8 tiles touching <= kGroupRows distinct rows
-    std::vector<int> gt0;
-    std::vector<int> grows;
-    std::vector<int> gn;
+    // groups of <= tiles_per_group tiles touching <= group_cap distinct rows
+    std::vector<int> gt0, grows, gn;
     std::vector<unsigned short> lj((size_t)nt * 16), lk((size_t)nt * 16);
     std::vector<int> stamp(U, -1), local(U, 0);
     int t = 0;
@@ -260,8 +538,7 @@ hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err)
         gt0.push_back(t);
         std::vector<int> rows;
         int ntg = 0;
-        while (t < nt && ntg < kPairsPerGroup / 16) {
-            int add = 0;
+        while (t < nt && ntg < tiles_per_group) {
             int seen[32];
             int ns = 0;
             for (int e = 0; e < 16; ++e) {
@@ -269,10 +546,10 @@ hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err)
                     if (stamp[v] == g) continue;
                     bool dup = false;
                     for (int s = 0; s < ns; ++s) dup |= (seen[s] == v);
-                    if (!dup) { seen[ns++] = v; ++add; }
+                    if (!dup) seen[ns++] = v;
                 }
             }
-            if ((int)rows.size() + add > kGroupRows) break;
+            if ((int)rows.size() + ns > group_cap) break;
             for (int s = 0; s < ns; ++s) {
                 stamp[seen[s]] = g;
                 local[seen[s]] = (int)rows.size();
@@ -286,7 +563,7 @@ hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err)
             ++ntg;
         }
         gn.push_back((int)rows.size());
-        rows.resize(kGroupRows, 0);
+        rows.resize(group_cap, 0);
         grows.insert(grows.end(), rows.begin(), rows.end());
     }
     plan.ngroups = (int)gt0.size();
@@ -295,13 +572,13 @@ hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err)
     for (int g = 0; g < plan.ngroups; ++g) {
         int mj = 0;
         for (int tt = gt0[g]; tt < gt0[g + 1]; ++tt) mj = std::max(mj, maxj[tt]);
-        for (int rb = 0; rb <= mj / kRowBlock; ++rb) tasks.push_back(make_int2(g, rb));
+        for (int rb = 0; rb <= mj / rowblock; ++rb) tasks.push_back(make_int2(g, rb));
     }
     plan.ntasks = (int)tasks.size();
 
     hipError_t e = hipSuccess;
     auto up = [&](auto *&dst, const auto &src) {
-        using T = std::remove_reference_t<decltype(src[0])>;
+        using T = std::remove_cv_t<std::remove_reference_t<decltype(src[0])>>;
         if (e != hipSuccess) return;
         e = hipMalloc((void **)&dst, sizeof(T) * std::max<size_t>(src.size(), 1));
         if (e == hipSuccess && !src.empty())
@@ -310,7 +587,7 @@ hipError_t build_triple_plan(int U, TriplePlan &plan, std::string &err)
     up(plan.tile_maxj, maxj);
     up(plan.tile_off, toff);
     up(plan.group_tile0, gt0);
-    up(plan.group_rows, grows);
+    up(plan.group_rows_idx, grows);
     up(plan.group_nrows, gn);
     up(plan.pair_lj, lj);
     up(plan.pair_lk, lk);
@@ -327,7 +604,7 @@ void free_triple_plan(TriplePlan &p)
     (void)hipFree(p.tile_maxj);
     (void)hipFree(p.tile_off);
     (void)hipFree(p.group_tile0);
-    (void)hipFree(p.group_rows);
+    (void)hipFree(p.group_rows_idx);
     (void)hipFree(p.group_nrows);
     (void)hipFree(p.pair_lj);
     (void)hipFree(p.pair_lk);
@@ -341,12 +618,13 @@ static TripleArgs args_of(const TriplePlan &p, int64_t ldz, int64_t nz)
     a.tile_maxj = p.tile_maxj;
     a.tile_off = p.tile_off;
     a.group_tile0 = p.group_tile0;
-    a.group_rows = p.group_rows;
+    a.group_rows = p.group_rows_idx;
     a.group_nrows = p.group_nrows;
     a.pair_lj = p.pair_lj;
     a.pair_lk = p.pair_lk;
     a.tasks = p.tasks;
     a.ntasks = p.ntasks;
+    a.group_cap = p.group_rows;
     a.ldz = ldz;
     a.nz = nz;
     return a;
@@ -355,8 +633,33 @@ static TripleArgs args_of(const TriplePlan &p, int64_t ldz, int64_t nz)
 hipError_t launch_triple_f64(const TriplePlan &plan, int64_t ldz, int64_t nz, const double *St,
                              double *T, hipStream_t s)
 {
-    if (nz % ZC != 0 || ldz % 2 != 0) return hipErrorInvalidValue;
+    if (nz % ZC != 0 || ldz % 2 != 0 || plan.rowblock != F64_ROWBLOCK ||
+        plan.tiles_per_group != F64_TILES || plan.group_rows != F64_GROUP_ROWS)
+        return hipErrorInvalidValue;
+    if (plan.ntasks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_triple_f64, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, ldz, nz), St, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t ldz, int nr, int nmu_pad,
+                               const float *S32, const uint16_t *SA, double *T, hipStream_t s)
+{
+    if (nmu_pad % MX_KZ != 0 || ldz != (int64_t)nr * nmu_pad || plan.rowblock != MX_ROWBLOCK ||
+        plan.tiles_per_group != MX_TILES || plan.group_rows != MX_GROUP_ROWS)
+        return hipErrorInvalidValue;
+    if (plan.ntasks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_triple_mixed, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, ldz, ldz), nr,
+                       nmu_pad / MX_KZ, S32, SA, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_bf16(int64_t nrows, int64_t ldz, const double *St, float *S32, uint16_t *SA,
+                             hipStream_t s)
+{
+    if (ldz % 8 != 0) return hipErrorInvalidValue;
+    const int64_t nb = nrows * (ldz / 8);
+    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, nrows, ldz, St,
+                       S32, SA);
     return hipGetLastError();
 }
 
@@ -367,17 +670,6 @@ hipError_t launch_gather(int kind, int ta, int tp, const int *tri_a, const int *
     hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kind, ta, tp,
                        tri_a, tri_p, np, plan.U, plan.tile_off, T, gamma);
     return hipGetLastError();
-}
-
-hipError_t launch_triple_mixed(const TriplePlan &, int64_t, int, int, const float *, const uint16_t *,
-                               const uint16_t *, double *, hipStream_t)
-{
-    return hipErrorNotSupported;
-}
-
-hipError_t launch_split_bf16(int64_t, const double *, float *, uint16_t *, uint16_t *, hipStream_t)
-{
-    return hipErrorNotSupported;
 }
 
 }  // namespace mp

@@ -274,3 +274,49 @@ def test_workspace_limit(mp, ctx):
         mp.projection_from_inputs(c2, inp).gamma()
     assert e.value.status == 3
     c2.close()
+
+
+# ------------------------------------------------------------------ mixed path
+@pytest.mark.parametrize("kind,n1,lmax,nr,nk", [
+    ("ordered", 5, 40, 21, 150),
+    ("symmetric", 5, 40, 21, 150),
+    ("symmetric", 7, 33, 9, 70),
+    ("ordered", 1, 20, 4, 40),
+    ("symmetric", 17, 24, 5, 60),     # U = 289: two 256-row super-blocks
+])
+def test_gamma_mixed_small(mp, ctx, oracle, kind, n1, lmax, nr, nk):
+    inp = _small(kind=kind, n1=n1, lmax=lmax, nr=nr, nk=nk)
+    pr = mp.projection_from_inputs(ctx, inp)
+    g = _np(pr.gamma("mixed"))
+    ref = oracle.gamma_full(inp)
+    err = normwise(g, ref)
+    print(f"mixed normwise error {err:.3e}")
+    assert err <= MIXED_BAR
+
+
+def test_gamma_mixed_config1_full(mp, ctx, oracle):
+    inp = synth.make_inputs(synth.CONFIGS[1])
+    pr = mp.projection_from_inputs(ctx, inp)
+    g = _np(pr.gamma("mixed"))
+    ref = oracle.gamma_full(inp)
+    err = normwise(g, ref)
+    print(f"mixed normwise error at lmax=64: {err:.3e}")
+    assert err <= MIXED_BAR
+
+
+def test_gamma_mixed_vs_fp64_config2(mp, ctx, oracle):
+    """lmax = 500: the mixed path against the FP64 path (itself pinned to
+    the oracle by test_gamma_config2_sampled), and against sampled oracle
+    entries."""
+    cfg = synth.CONFIGS[2]
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    g64 = _np(pr.gamma("fp64"))
+    gm = _np(pr.gamma("mixed"))
+    err = normwise(gm, g64)
+    print(f"mixed vs fp64 normwise error at lmax=500: {err:.3e}")
+    assert err <= MIXED_BAR
+    idx = synth.pick_entries(cfg, gm.shape, 8, seed_offset=7)
+    rows, cols = np.unravel_index(idx, gm.shape)
+    ref = oracle.gamma_entries(inp, rows, cols)
+    assert np.abs(gm[rows, cols] - ref).max() <= MIXED_BAR * np.abs(g64).max()
