@@ -211,6 +211,25 @@ void zero(modal_ctx c, double *p, int64_t n)
     hipck(c, hipGetLastError(), "zero fill");
 }
 
+// Zero the padding rows U..upad of every 32-wide z block of a z-blocked array.
+__global__ void k_zero_pad_rows(double *St, int64_t nzb, int64_t upad, int64_t U)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (upad - U) * 32;
+    if (i >= nzb * per) return;
+    const int64_t zb = i / per, rem = i % per;
+    St[(zb * upad + U) * 32 + rem] = 0.0;
+}
+
+void zero_pad_rows(modal_ctx c, double *St, int64_t ldz, int64_t upad, int64_t U)
+{
+    const int64_t n = (ldz / 32) * (upad - U) * 32;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_pad_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, St,
+                       ldz / 32, upad, U);
+    hipck(c, hipGetLastError(), "zero fill");
+}
+
 // ---- validation -------------------------------------------------------------
 struct Dims {
     int L, nk, nr, nmu, ldmu, np, na, U;
@@ -404,13 +423,14 @@ void run_triple_gather(modal_ctx c, const modal_problem *p, const Dims &d, modal
     {
         StageTimer tm(c, MODAL_STAGE_TRIPLE);
         if (prec == MODAL_FP64) {
-            hipck(c, launch_triple_f64(plan, ldz, ldz, St, T, c->stream), "triple f64");
+            hipck(c, launch_triple_f64(plan, pad_to(d.U, kRowPad), ldz, St, T, c->stream), "triple f64");
         } else {
             const size_t n = (size_t)pad_to(d.U, kRowPad) * ldz;
             float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * n);
             uint16_t *sa = (uint16_t *)ws_get(c, W_SH, 2 * sizeof(uint16_t) * n);
-            hipck(c, launch_split_bf16(pad_to(d.U, kRowPad), ldz, St, s32, sa, c->stream), "split");
-            hipck(c, launch_triple_mixed(plan, ldz, d.nr, d.ldmu, s32, sa, T, c->stream), "triple mixed");
+            hipck(c, launch_split_bf16((int64_t)n, St, s32, sa, c->stream), "split");
+            hipck(c, launch_triple_mixed(plan, pad_to(d.U, kRowPad), ldz, d.nr, d.ldmu, s32, sa, T, c->stream),
+                  "triple mixed");
         }
     }
     const int *ta = dev_in(c, p->tri_a, (size_t)p->ta * 3);
@@ -658,8 +678,8 @@ modal_status modal_S(modal_ctx c, const modal_grid *g, const modal_problem *p, m
         OutBuf o = dev_out(c, S, (size_t)d.U * d.nr * d.nmu, W_ST);
         StageTimer tm(c, MODAL_STAGE_S);
         hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, cl, wl, c->stream), "weights");
-        hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.nmu, d.L, wl, ql, dbeta, P, d.nmu, nullptr, o.dev,
-                               c->stream),
+        hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.nmu, d.L, wl, ql, dbeta, P, d.nmu, nullptr, 0,
+                               o.dev, c->stream),
               "S gemm");
         finish_out(c, o);
     });
@@ -684,8 +704,8 @@ modal_status modal_gamma_from_S(modal_ctx c, const modal_grid *g, const modal_pr
         {
             StageTimer tm(c, MODAL_STAGE_S);
             hipck(c, launch_cbrt_weights(d.nr, d.nmu, d.ldmu, G.r, G.wr, G.wmu, wz, c->stream), "weights");
-            hipck(c, launch_s_import(d.U, d.nr, d.nmu, d.ldmu, dS, wz, St, c->stream), "S import");
-            zero(c, St + (size_t)d.U * ldz, (int64_t)(Upad - d.U) * ldz);
+            zero_pad_rows(c, St, ldz, Upad, d.U);
+            hipck(c, launch_s_import(d.U, Upad, d.nr, d.nmu, d.ldmu, dS, wz, St, c->stream), "S import");
         }
         run_triple_gather(c, p, d, prec, St, o.dev);
         finish_out(c, o);
@@ -726,10 +746,11 @@ modal_status modal_gamma(modal_ctx c, const modal_grid *g, const modal_problem *
             StageTimer tm(c, MODAL_STAGE_S);
             hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, cl, wl, c->stream), "weights");
             hipck(c, launch_cbrt_weights(d.nr, d.nmu, d.ldmu, G.r, G.wr, G.wmu, wz, c->stream), "cbrt weights");
-            hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.ldmu, d.L, wl, ql, beta, P, d.ldmu, wz, St,
+            // the padding rows U..Upad of every z block must read as zero
+            zero_pad_rows(c, St, ldz, Upad, d.U);
+            hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.ldmu, d.L, wl, ql, beta, P, d.ldmu, wz, Upad, St,
                                    c->stream),
                   "S gemm");
-            zero(c, St + (size_t)d.U * ldz, (int64_t)(Upad - d.U) * ldz);
         }
         // (d) triple products and Gamma
         run_triple_gather(c, p, d, prec, St, o.dev);

@@ -54,23 +54,24 @@ hipError_t launch_beta_gemm(int nl, int l0, int lmin, int L, int nk, int nr, int
                             const double *Jd, const double *k, const double *wk,
                             const double *qk, double *beta, hipStream_t s);
 
-// Step c: S rows.  Output row u = a * np + p holds, for each r, nmu values
-// (padded to ldmu; padded entries are zero).  If wz != NULL the output is
-// scaled by wz[r * ldmu + mu] (the cube root of the quadrature weight).
+// Step c: S rows.  Row u = a * np + p holds, for each r, ldmu values (zero
+// past nmu).  upad == 0: caller layout S[u][r][ldmu], unscaled.  upad > 0:
+// scaled by wz[z] (the cube root of the quadrature weight) and z-blocked,
+// St[z / 32][u][z % 32] with z = r * ldmu + mu and upad rows per block.
 hipError_t launch_s_gemm(int na, int np, int nr, int nmu, int ldmu, int L,
                          const double *wl, const double *ql, const double *beta,
-                         const double *P, int ldP, const double *wz, double *S, hipStream_t s);
+                         const double *P, int ldP, const double *wz, int64_t upad, double *S,
+                         hipStream_t s);
 hipError_t launch_weights_l(int L, int lmin, double v_power, const double *cl, double *wl,
                             hipStream_t s);
 hipError_t launch_cbrt_weights(int nr, int nmu, int ldmu, const double *r, const double *wr,
                                const double *wmu, double *wz, hipStream_t s);
-// S in the caller's layout [u][r][nmu] -> scaled, padded rows.
-hipError_t launch_s_import(int64_t nu, int nr, int nmu, int ldmu, const double *S,
+// S in the caller's layout [u][r][nmu] -> scaled, z-blocked rows.
+hipError_t launch_s_import(int64_t nu, int64_t upad, int nr, int nmu, int ldmu, const double *S,
                            const double *wz, double *St, hipStream_t s);
-hipError_t launch_s_export(int64_t nu, int nr, int nmu, int ldmu, const double *St,
-                           double *S, hipStream_t s);
 
-// Step d: unique third moments T[i<=j<=k] = Sum_z St_i St_j St_k.
+// Step d: unique third moments T[i<=j<=k] = Sum_z St_i St_j St_k of the
+// z-blocked rows St[z / 32][Upad][32] (Upad = rows padded to kRowPad).
 // A plan lists the 16-pair column tiles, their packing offsets in T (shared
 // by every plan of the same U), and the workgroup tasks of one kernel shape:
 // groups of `tiles_per_group` column tiles touching at most `group_rows`
@@ -102,15 +103,18 @@ void free_triple_plan(TriplePlan &plan);
 void triple_f64_shape(int &rowblock, int &tiles_per_group, int &group_rows);
 void triple_mixed_shape(int &rowblock, int &tiles_per_group, int &group_rows);
 
-hipError_t launch_triple_f64(const TriplePlan &plan, int64_t ldz, int64_t nz,
+hipError_t launch_triple_f64(const TriplePlan &plan, int64_t upad, int64_t ldz,
                              const double *St, double *T, hipStream_t s);
 // Mixed: S32 is the FP32 copy of the scaled rows (sources of the generated
-// operand) and SA the BF16 (hi, lo) split packed per 8 z values
-// ([row][z/8][8 hi, 8 lo]); each r holds nmu_pad z values (a multiple of 32).
-hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t ldz, int nr, int nmu_pad,
-                               const float *S32, const uint16_t *SA, double *T, hipStream_t s);
-hipError_t launch_split_bf16(int64_t nrows, int64_t ldz, const double *St, float *S32,
-                             uint16_t *SA, hipStream_t s);
+// operand, same z-blocked layout) and SA their BF16 (hi, lo) split packed
+// per 8 z values ([z / 32][Upad][4][8 hi, 8 lo]); each r holds nmu_pad z
+// values (a multiple of 32).
+hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t upad, int64_t ldz, int nr,
+                               int nmu_pad, const float *S32, const uint16_t *SA, double *T,
+                               hipStream_t s);
+// Elementwise over the n values (a multiple of 8): FP32 copy and BF16 split.
+hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *SA,
+                             hipStream_t s);
 
 // Gather Gamma entries from T.
 hipError_t launch_gather(int kind, int ta, int tp, const int *tri_a, const int *tri_p,

@@ -13,7 +13,11 @@
 //   rows r, columns mu, depth l; the first factor is formed on load.  The
 //   epilogue optionally multiplies by the cube root of the quadrature weight
 //   W(r, mu) = wr r^2 wmu, so that the triple product of three scaled rows
-//   carries W once.
+//   carries W once, and then writes the rows z-blocked: St[z / 32][u][z % 32]
+//   with z = r * ldmu + mu, so that one 32-wide z step of every row is one
+//   contiguous slab (the triple-product kernels read a few hundred rows per
+//   step; with whole rows contiguous each step would touch a few hundred
+//   pages).
 #include "internal.hpp"
 
 namespace mp {
@@ -139,6 +143,7 @@ struct SOp {
     int np, nmu, ldP;
     const double *wl, *ql, *beta, *P, *wz;
     double *S;
+    int64_t upad;                             // > 0: z-blocked output (see below)
     __device__ double a(int u, int m, int l) const
     {
         const int ia = u / np, ip = u % np;
@@ -147,9 +152,14 @@ struct SOp {
     __device__ double bv(int, int l, int n) const { return P[(size_t)l * ldP + n]; }
     __device__ void store(int u, int m, int n, double v) const
     {
-        const size_t o = ((size_t)u * M + m) * N + n;
-        if (n >= nmu) { S[o] = 0.0; return; }
-        S[o] = wz ? v * wz[(size_t)m * N + n] : v;
+        if (upad > 0) {
+            // z-blocked rows: St[z / 32][u][z % 32], z = r * ldmu + mu
+            const int64_t z = (int64_t)m * N + n;
+            const size_t o = (((size_t)(z >> 5) * upad + u) << 5) + (z & 31);
+            S[o] = (n < nmu) ? v * wz[z] : 0.0;
+            return;
+        }
+        S[((size_t)u * M + m) * N + n] = (n < nmu) ? v : 0.0;
     }
 };
 
@@ -172,27 +182,19 @@ __global__ void k_cbrt_weights(int nr, int nmu, int ldmu, const double *__restri
     wz[i] = (im < nmu) ? cbrt(wr[ir] * r[ir] * r[ir] * wmu[im]) : 0.0;
 }
 
-__global__ void k_s_import(int64_t nu, int nr, int nmu, int ldmu, const double *__restrict__ S,
-                           const double *__restrict__ wz, double *__restrict__ St)
+__global__ void k_s_import(int64_t nu, int64_t upad, int nr, int nmu, int ldmu,
+                           const double *__restrict__ S, const double *__restrict__ wz,
+                           double *__restrict__ St)
 {
+    // caller layout S[u][r][nmu] -> z-blocked St[z / 32][u][z % 32], scaled
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = nu * nr * ldmu;
+    const int64_t ldz = (int64_t)nr * ldmu;
+    const int64_t n = nu * ldz;
     if (i >= n) return;
-    const int im = (int)(i % ldmu);
-    const int64_t ur = i / ldmu;                  // u * nr + r
-    const int ir = (int)(ur % nr);
-    St[i] = (im < nmu) ? S[ur * nmu + im] * wz[(size_t)ir * ldmu + im] : 0.0;
-}
-
-__global__ void k_s_export(int64_t nu, int nr, int nmu, int ldmu, const double *__restrict__ St,
-                           double *__restrict__ S)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = nu * nr * nmu;
-    if (i >= n) return;
-    const int im = (int)(i % nmu);
-    const int64_t ur = i / nmu;
-    S[i] = St[ur * ldmu + im];
+    const int64_t u = i / ldz, z = i % ldz;
+    const int ir = (int)(z / ldmu), im = (int)(z % ldmu);
+    St[(((z >> 5) * upad + u) << 5) + (z & 31)] =
+        (im < nmu) ? S[(u * nr + ir) * nmu + im] * wz[z] : 0.0;
 }
 
 template <class Op>
@@ -216,9 +218,10 @@ hipError_t launch_beta_gemm(int nl, int l0, int lmin, int L, int nk, int nr, int
 
 hipError_t launch_s_gemm(int na, int np, int nr, int nmu, int ldmu, int L, const double *wl,
                          const double *ql, const double *beta, const double *P, int ldP,
-                         const double *wz, double *S, hipStream_t s)
+                         const double *wz, int64_t upad, double *S, hipStream_t s)
 {
-    SOp op{nr, ldmu, L, np, nmu, ldP, wl, ql, beta, P, wz, S};
+    if (upad > 0 && (!wz || ldmu % 32 != 0)) return hipErrorInvalidValue;
+    SOp op{nr, ldmu, L, np, nmu, ldP, wl, ql, beta, P, wz, S, upad};
     return run(op, na * np, s);
 }
 
@@ -238,21 +241,13 @@ hipError_t launch_cbrt_weights(int nr, int nmu, int ldmu, const double *r, const
     return hipGetLastError();
 }
 
-hipError_t launch_s_import(int64_t nu, int nr, int nmu, int ldmu, const double *S, const double *wz,
-                           double *St, hipStream_t s)
+hipError_t launch_s_import(int64_t nu, int64_t upad, int nr, int nmu, int ldmu, const double *S,
+                           const double *wz, double *St, hipStream_t s)
 {
+    if (ldmu % 32 != 0) return hipErrorInvalidValue;
     const int64_t n = nu * nr * ldmu;
-    hipLaunchKernelGGL(k_s_import, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nu, nr, nmu,
+    hipLaunchKernelGGL(k_s_import, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nu, upad, nr, nmu,
                        ldmu, S, wz, St);
-    return hipGetLastError();
-}
-
-hipError_t launch_s_export(int64_t nu, int nr, int nmu, int ldmu, const double *St, double *S,
-                           hipStream_t s)
-{
-    const int64_t n = nu * nr * nmu;
-    hipLaunchKernelGGL(k_s_export, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nu, nr, nmu,
-                       ldmu, St, S);
     return hipGetLastError();
 }
 

@@ -80,8 +80,17 @@ struct TripleArgs {
     const int2 *tasks;
     int ntasks;
     int group_cap;
-    int64_t ldz, nz;
+    int64_t upad;          // rows per z block of the z-blocked S layout
+    int64_t nz;            // z values (nr * nmu_pad)
 };
+
+// Barrier for LDS traffic only: unlike __syncthreads() it does not wait for
+// outstanding global loads, so prefetches stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);      // lgkmcnt(0); vmcnt and expcnt unconstrained
+    __builtin_amdgcn_s_barrier();
+}
 
 // ============================================================================
 // FP64
@@ -132,18 +141,20 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
     // group rows <= 160 x 16 z = 1280 double2 (<= 5 per thread)
     double2 pa[4], pg[5];
     auto gload = [&](int64_t z0) {
+        // z-blocked rows: element (row, z) at ((z / 32) * upad + row) * 32 + z % 32
+        const size_t zbase = (((size_t)(z0 >> 5) * A.upad) << 5) + (z0 & 31);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int idx = t + 256 * i;
             const int row = idx >> 3, zp = idx & 7;
-            pa[i] = *reinterpret_cast<const double2 *>(St + (size_t)(row0 + row) * A.ldz + z0 + 2 * zp);
+            pa[i] = *reinterpret_cast<const double2 *>(St + zbase + ((size_t)(row0 + row) << 5) + 2 * zp);
         }
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
             const int idx = t + 256 * i;
             const int row = idx >> 3, zp = idx & 7;
             if (row < ngr)
-                pg[i] = *reinterpret_cast<const double2 *>(St + (size_t)grow[row] * A.ldz + z0 + 2 * zp);
+                pg[i] = *reinterpret_cast<const double2 *>(St + zbase + ((size_t)grow[row] << 5) + 2 * zp);
         }
     };
     auto lstore = [&](int buf) {
@@ -168,7 +179,7 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
     const int64_t nchunks = A.nz / ZC;
     gload(0);
     lstore(0);
-    __syncthreads();
+    lds_barrier();
     for (int64_t c = 0; c < nchunks; ++c) {
         const int buf = (int)(c & 1);
         if (c + 1 < nchunks) gload((c + 1) * ZC);
@@ -188,7 +199,7 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
                         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
         if (c + 1 < nchunks) lstore(buf ^ 1);
-        __syncthreads();
+        lds_barrier();
     }
 
     // FP64 16x16x4 result layout: lane l, element q -> row 4q + l/16, column l%16
@@ -294,14 +305,14 @@ __global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int 
             tot[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
 
-    const int64_t ldzb = A.ldz / 8;                  // 8-z blocks per row
     const int64_t nsteps = A.nz / MX_KZ;
-    // A fragments: row row0 + 16 i + n, z block 4 s + zg
+    // A fragments of step s: row row0 + 16 i + n, 8-z group zg, at
+    // SA[((s * upad + row) * 4 + zg) * 16]
     auto aload = [&](int64_t s, Frag (&f)[4]) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint4 *p = reinterpret_cast<const uint4 *>(
-                SA + (((size_t)(row0 + 16 * i + n) * ldzb + 4 * s + zg) << 4));
+                SA + ((((size_t)s * A.upad + row0 + 16 * i + n) * 4 + zg) << 4));
             f[i].hi = p[0];
             f[i].lo = p[1];
         }
@@ -315,7 +326,7 @@ __global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int 
             const int idx = t + 256 * i;
             const int row = idx >> 3, q = idx & 7;
             if (row < ngr)
-                sreg[i] = *reinterpret_cast<const float4 *>(S32 + (size_t)grow[row] * A.ldz + s * MX_KZ + 4 * q);
+                sreg[i] = *reinterpret_cast<const float4 *>(S32 + (((size_t)s * A.upad + grow[row]) << 5) + 4 * q);
         }
     };
     auto sstore = [&](int buf) {
@@ -348,11 +359,11 @@ __global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int 
         sload(1);
         sstore(1);
     }
-    __syncthreads();
+    lds_barrier();
     bgen(0);
     if (nsteps > 2) sload(2);
     aload(0, acur);
-    __syncthreads();
+    lds_barrier();
 
     int rcount = 0;                                  // completed r values
     int kin = 0;                                     // step within the current r
@@ -411,17 +422,18 @@ __global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int 
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) acur[i] = anext[i];
-        __syncthreads();
+        lds_barrier();
     }
 }
 
-__global__ void k_split_bf16(int64_t nrows, int64_t ldz, const double *__restrict__ St,
-                             float *__restrict__ S32, uint16_t *__restrict__ SA)
+__global__ void k_split_bf16(int64_t nblk, const double *__restrict__ St, float *__restrict__ S32,
+                             uint16_t *__restrict__ SA)
 {
-    // one thread per 8-z block of a row
+    // one thread per 8 consecutive values (the same 8 z of one row in the
+    // z-blocked layout): FP32 copy, and BF16 high parts of the FP32 values
+    // with the BF16 rounding of the FP64 remainders
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nb = nrows * (ldz / 8);
-    if (i >= nb) return;
+    if (i >= nblk) return;
     const double *src = St + i * 8;
     float f[8];
     uint32_t h[4], l[4];
@@ -612,7 +624,7 @@ void free_triple_plan(TriplePlan &p)
     p = TriplePlan{};
 }
 
-static TripleArgs args_of(const TriplePlan &p, int64_t ldz, int64_t nz)
+static TripleArgs args_of(const TriplePlan &p, int64_t upad, int64_t nz)
 {
     TripleArgs a;
     a.tile_maxj = p.tile_maxj;
@@ -625,41 +637,40 @@ static TripleArgs args_of(const TriplePlan &p, int64_t ldz, int64_t nz)
     a.tasks = p.tasks;
     a.ntasks = p.ntasks;
     a.group_cap = p.group_rows;
-    a.ldz = ldz;
+    a.upad = upad;
     a.nz = nz;
     return a;
 }
 
-hipError_t launch_triple_f64(const TriplePlan &plan, int64_t ldz, int64_t nz, const double *St,
+hipError_t launch_triple_f64(const TriplePlan &plan, int64_t upad, int64_t ldz, const double *St,
                              double *T, hipStream_t s)
 {
-    if (nz % ZC != 0 || ldz % 2 != 0 || plan.rowblock != F64_ROWBLOCK ||
+    if (ldz % 32 != 0 || upad % F64_ROWBLOCK != 0 || upad < plan.U || plan.rowblock != F64_ROWBLOCK ||
         plan.tiles_per_group != F64_TILES || plan.group_rows != F64_GROUP_ROWS)
         return hipErrorInvalidValue;
     if (plan.ntasks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_triple_f64, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, ldz, nz), St, T);
+    hipLaunchKernelGGL(k_triple_f64, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, upad, ldz), St, T);
     return hipGetLastError();
 }
 
-hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t ldz, int nr, int nmu_pad,
+hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t upad, int64_t ldz, int nr, int nmu_pad,
                                const float *S32, const uint16_t *SA, double *T, hipStream_t s)
 {
-    if (nmu_pad % MX_KZ != 0 || ldz != (int64_t)nr * nmu_pad || plan.rowblock != MX_ROWBLOCK ||
-        plan.tiles_per_group != MX_TILES || plan.group_rows != MX_GROUP_ROWS)
+    if (nmu_pad % MX_KZ != 0 || ldz != (int64_t)nr * nmu_pad || upad % MX_ROWBLOCK != 0 ||
+        upad < plan.U || plan.rowblock != MX_ROWBLOCK || plan.tiles_per_group != MX_TILES ||
+        plan.group_rows != MX_GROUP_ROWS)
         return hipErrorInvalidValue;
     if (plan.ntasks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_triple_mixed, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, ldz, ldz), nr,
+    hipLaunchKernelGGL(k_triple_mixed, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, upad, ldz), nr,
                        nmu_pad / MX_KZ, S32, SA, T);
     return hipGetLastError();
 }
 
-hipError_t launch_split_bf16(int64_t nrows, int64_t ldz, const double *St, float *S32, uint16_t *SA,
-                             hipStream_t s)
+hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *SA, hipStream_t s)
 {
-    if (ldz % 8 != 0) return hipErrorInvalidValue;
-    const int64_t nb = nrows * (ldz / 8);
-    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, nrows, ldz, St,
-                       S32, SA);
+    if (n % 8 != 0) return hipErrorInvalidValue;
+    const int64_t nb = n / 8;
+    hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, nb, St, S32, SA);
     return hipGetLastError();
 }
 
