@@ -35,8 +35,8 @@
 // memory, and generates one column tile of the product operand per 32-wide
 // z step (FP32 product of two FP32 rows, then split), shared with the other
 // waves through LDS.  Each r's mu sum is accumulated in FP32 by the matrix
-// cores; the per-r sums are added in FP32 for blocks of kRBlock radial
-// points, and the blocks are accumulated in FP64 in T.  The mu sum of an r is
+// cores and then added to the FP64 r sum held in T (the workgroup owns its
+// outputs, so this is a plain read-modify-write).  The mu sum of an r is
 // always complete before it enters the r sum (Sec. 2.2).
 #include "internal.hpp"
 
@@ -54,7 +54,6 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 // ---- shapes -----------------------------------------------------------------
 constexpr int F64_ROWBLOCK = 128, F64_TILES = 8, F64_GROUP_ROWS = 160;
 constexpr int MX_ROWBLOCK = 256, MX_TILES = 4, MX_GROUP_ROWS = 96;
-constexpr int kRBlock = 16;                  // radial points per FP32 block (mixed)
 
 constexpr int ZC = 16;                       // z values per staged chunk (FP64)
 constexpr int LDSA = F64_ROWBLOCK + 1;       // padded LDS row lengths (doubles)
@@ -111,7 +110,9 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
     const int *grow = A.group_rows + (size_t)g * A.group_cap;
     const int row0 = rb * F64_ROWBLOCK;
 
-    // this lane's four pairs (one per column tile of the wave)
+    // this lane's four pairs (one per column tile of the wave); tiles past the
+    // group's end and row blocks past a tile's max j are computed (their
+    // operands are valid rows) but never stored
     int lj[4], lk[4];
     unsigned mask = 0;
 #pragma unroll
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
         }
     }
     mask = __builtin_amdgcn_readfirstlane(mask);
+    const bool active = mask != 0;               // wave-uniform
 
     d4 acc[4][4];
 #pragma unroll
@@ -137,25 +139,28 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // staging: A rows 128 x 16 z = 1024 double2 (4 per thread);
-    // group rows <= 160 x 16 z = 1280 double2 (<= 5 per thread)
+    // staging: A rows 128 x 16 z = 1024 double2 (4 per thread); group rows
+    // (padded to 160 with valid row indices) x 16 z = 1280 double2 (5 per
+    // thread).  Row offsets are fixed for the whole z loop.
+    size_t aoff[4], goff[5];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = t + 256 * i;
+        aoff[i] = ((size_t)(row0 + (idx >> 3)) << 5) + 2 * (idx & 7);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int idx = t + 256 * i;
+        goff[i] = ((size_t)grow[idx >> 3] << 5) + 2 * (idx & 7);
+    }
     double2 pa[4], pg[5];
     auto gload = [&](int64_t z0) {
         // z-blocked rows: element (row, z) at ((z / 32) * upad + row) * 32 + z % 32
-        const size_t zbase = (((size_t)(z0 >> 5) * A.upad) << 5) + (z0 & 31);
+        const double *base = St + (((size_t)(z0 >> 5) * A.upad) << 5) + (z0 & 31);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int idx = t + 256 * i;
-            const int row = idx >> 3, zp = idx & 7;
-            pa[i] = *reinterpret_cast<const double2 *>(St + zbase + ((size_t)(row0 + row) << 5) + 2 * zp);
-        }
+        for (int i = 0; i < 4; ++i) pa[i] = *reinterpret_cast<const double2 *>(base + aoff[i]);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            const int idx = t + 256 * i;
-            const int row = idx >> 3, zp = idx & 7;
-            if (row < ngr)
-                pg[i] = *reinterpret_cast<const double2 *>(St + zbase + ((size_t)grow[row] << 5) + 2 * zp);
-        }
+        for (int i = 0; i < 5; ++i) pg[i] = *reinterpret_cast<const double2 *>(base + goff[i]);
     };
     auto lstore = [&](int buf) {
 #pragma unroll
@@ -169,10 +174,8 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
         for (int i = 0; i < 5; ++i) {
             const int idx = t + 256 * i;
             const int row = idx >> 3, zp = idx & 7;
-            if (row < ngr) {
-                Sg[buf][2 * zp][row] = pg[i].x;
-                Sg[buf][2 * zp + 1][row] = pg[i].y;
-            }
+            Sg[buf][2 * zp][row] = pg[i].x;
+            Sg[buf][2 * zp + 1][row] = pg[i].y;
         }
     };
 
@@ -183,20 +186,21 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
     for (int64_t c = 0; c < nchunks; ++c) {
         const int buf = (int)(c & 1);
         if (c + 1 < nchunks) gload((c + 1) * ZC);
+        if (active) {
 #pragma unroll
-        for (int ks = 0; ks < ZC / 4; ++ks) {
-            const int z = ks * 4 + (lane >> 4);
-            double av[4], bv[4];
+            for (int ks = 0; ks < ZC / 4; ++ks) {
+                const int z = ks * 4 + (lane >> 4);
+                double av[4], bv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = Sa[buf][z][wm * 64 + i * 16 + (lane & 15)];
+                for (int i = 0; i < 4; ++i) av[i] = Sa[buf][z][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Sg[buf][z][lj[j]] * Sg[buf][z][lk[j]];
+                for (int j = 0; j < 4; ++j) bv[j] = Sg[buf][z][lj[j]] * Sg[buf][z][lk[j]];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (mask & (1u << (i * 4 + j)))
+                    for (int j = 0; j < 4; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+            }
         }
         if (c + 1 < nchunks) lstore(buf ^ 1);
         lds_barrier();
@@ -273,15 +277,14 @@ __global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int 
     const int2 tk = A.tasks[task];
     const int g = tk.x, rb = tk.y;
     const int t0 = A.group_tile0[g], nt = A.group_tile0[g + 1] - t0;
-    const int ngr = A.group_nrows[g];
     const int *grow = A.group_rows + (size_t)g * A.group_cap;
     const int row0 = rb * MX_ROWBLOCK + wave * 64;   // this wave's 64 rows
     const int n = lane & 15, zg = lane >> 4;
 
-    // the column tile this wave generates (tile index == wave)
-    const bool gen = wave < nt;
+    // the column tile this wave generates (tile index == wave); tiles past the
+    // group's end use valid rows (local 0) and are never stored
     int gj = 0, gk = 0;
-    if (gen) {
+    if (wave < nt) {
         const int q = (t0 + wave) * 16 + n;
         gj = A.pair_lj[q];
         gk = A.pair_lk[q];
@@ -295,50 +298,59 @@ __global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int 
             if (row0 + i * 16 <= mj) mask |= 1u << (i * CT + j);
     }
     mask = __builtin_amdgcn_readfirstlane(mask);
+    const bool active = mask != 0;                   // wave-uniform
+    // T blocks of this wave: tile j, row block (row0 >> 4) + i at tdst[j] + 256 i
+    double *tdst[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+        tdst[j] = T + ((size_t)(A.tile_off[t0 + (j < nt ? j : 0)] + (row0 >> 4)) << 8);
 
-    f4 acc[4][CT], tot[4][CT];
+    f4 acc[4][CT];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < CT; ++j) {
-            acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-            tot[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int j = 0; j < CT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int64_t nsteps = A.nz / MX_KZ;
     // A fragments of step s: row row0 + 16 i + n, 8-z group zg, at
     // SA[((s * upad + row) * 4 + zg) * 16]
-    auto aload = [&](int64_t s, Frag (&f)[4]) {
+    size_t arow[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) arow[i] = ((size_t)(row0 + 16 * i + n) * 4 + zg) << 4;
+    const size_t astep = (size_t)A.upad << 6;        // uint16 per step
+    auto aload = [&](int64_t s, uint4 (&h)[4], uint4 (&l)[4]) {
+        const uint16_t *base = SA + (size_t)s * astep;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(
-                SA + ((((size_t)s * A.upad + row0 + 16 * i + n) * 4 + zg) << 4));
-            f[i].hi = p[0];
-            f[i].lo = p[1];
+            const uint4 *p = reinterpret_cast<const uint4 *>(base + arow[i]);
+            h[i] = p[0];
+            l[i] = p[1];
         }
     };
-    // source rows of the group: ngr x 32 floats = ngr x 8 float4 (<= 3 per thread)
-    constexpr int SRC_PER = (MX_GROUP_ROWS * 8 + 255) / 256;
-    float4 sreg[SRC_PER];
-    auto sload = [&](int64_t s) {
+    // source rows of the group (padded to MX_GROUP_ROWS with valid rows):
+    // 96 rows x 32 floats = 768 float4, three per thread
+    constexpr int SRC_PER = MX_GROUP_ROWS * 8 / 256;
+    size_t soff[SRC_PER];
 #pragma unroll
-        for (int i = 0; i < SRC_PER; ++i) {
-            const int idx = t + 256 * i;
-            const int row = idx >> 3, q = idx & 7;
-            if (row < ngr)
-                sreg[i] = *reinterpret_cast<const float4 *>(S32 + (((size_t)s * A.upad + grow[row]) << 5) + 4 * q);
-        }
+    for (int i = 0; i < SRC_PER; ++i) {
+        const int idx = t + 256 * i;
+        soff[i] = ((size_t)grow[idx >> 3] << 5) + 4 * (idx & 7);
+    }
+    const size_t sstep = (size_t)A.upad << 5;         // floats per step
+    f4 sreg[SRC_PER];      // native vectors: HIP's float4 struct is not promoted to registers here
+    auto sload = [&](int64_t s) {
+        const float *base = S32 + (size_t)s * sstep;
+#pragma unroll
+        for (int i = 0; i < SRC_PER; ++i) sreg[i] = *reinterpret_cast<const f4 *>(base + soff[i]);
     };
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < SRC_PER; ++i) {
             const int idx = t + 256 * i;
-            const int row = idx >> 3, q = idx & 7;
-            if (row < ngr) *reinterpret_cast<float4 *>(&Src[buf][row][4 * q]) = sreg[i];
+            *reinterpret_cast<f4 *>(&Src[buf][idx >> 3][4 * (idx & 7)]) = sreg[i];
         }
     };
     auto bgen = [&](int buf) {
-        if (!gen) return;
         float v[8];
         const float *pj = &Src[buf][gj][8 * zg];
         const float *pk = &Src[buf][gk][8 * zg];
@@ -352,76 +364,89 @@ __global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int 
     };
 
     // prologue: sources of steps 0 and 1 in LDS, operand of step 0 generated
-    Frag acur[4], anext[4];
+    uint4 ah[4], al[4], nh[4], nl[4];
     sload(0);
     sstore(0);
-    if (nsteps > 1) {
-        sload(1);
-        sstore(1);
-    }
+    sload(nsteps > 1 ? 1 : 0);
+    sstore(1);
     lds_barrier();
     bgen(0);
-    if (nsteps > 2) sload(2);
-    aload(0, acur);
+    sload(nsteps > 2 ? 2 : nsteps - 1);
+    aload(0, ah, al);
     lds_barrier();
 
-    int rcount = 0;                                  // completed r values
     int kin = 0;                                     // step within the current r
     bool first_flush = true;
+    const int64_t last = nsteps - 1;
     for (int64_t s = 0; s < nsteps; ++s) {
         const int buf = (int)(s & 1);
-        if (s + 1 < nsteps) bgen(buf ^ 1);           // operand of step s + 1
-        if (s + 2 < nsteps) sstore(buf);             // sources of step s + 2
-        if (s + 3 < nsteps) sload(s + 3);
-        if (s + 1 < nsteps) aload(s + 1, anext);
+        // Past the last step these clamp to it and produce values that are
+        // never used; keeping them unconditional keeps the loop free of
+        // branches around the register-resident staging.
+        bgen(buf ^ 1);                               // operand of step s + 1
+        aload(s + 1 < last ? s + 1 : last, nh, nl);
+        sstore(buf);                                 // sources of step s + 2
+        sload(s + 3 < last ? s + 3 : last);
+        if (active) {
+            bf8 bh[CT], bl[CT];
 #pragma unroll
-        for (int j = 0; j < CT; ++j) {
-            const bf8 bh = as_bf8(Bb[buf][j][0][lane]);
-            const bf8 bl = as_bf8(Bb[buf][j][1][lane]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (!(mask & (1u << (i * CT + j)))) continue;
-                const bf8 ah = as_bf8(acur[i].hi), al = as_bf8(acur[i].lo);
-                f4 c = acc[i][j];
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
-                acc[i][j] = c;
+            for (int j = 0; j < CT; ++j) {
+                bh[j] = as_bf8(Bb[buf][j][0][lane]);
+                bl[j] = as_bf8(Bb[buf][j][1][lane]);
             }
+            // the three products, each over all tiles, so that consecutive
+            // matrix-core operations never depend on each other
+#pragma unroll
+            for (int j = 0; j < CT; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < CT; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < CT; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), bh[j], acc[i][j], 0, 0, 0);
         }
-        if (++kin == kpr) {                          // this r's mu sum is complete
+        if (++kin == kpr) {
+            // this r's mu sum is complete: add it to the FP64 r sum in T.
+            // All loads are issued before any add so their latencies overlap.
+            // (BF16 16x16x32 result layout: lane l, element q -> row 4(l/16) + q, column l%16)
             kin = 0;
-            ++rcount;
+            double old[4][CT][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < CT; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        old[i][j][q] = 0.0;
+                        if (!first_flush && (mask & (1u << (i * CT + j))))
+                            old[i][j][q] = tdst[j][(size_t)(i * 256 + (4 * zg + q) * 16 + n)];
+                    }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < CT; ++j) {
-                    tot[i][j] += acc[i][j];
+                    if (mask & (1u << (i * CT + j))) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            tdst[j][(size_t)(i * 256 + (4 * zg + q) * 16 + n)] =
+                                old[i][j][q] + (double)acc[i][j][q];
+                    }
                     acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
                 }
-            if (rcount % kRBlock == 0 || rcount == nr) {
-                // accumulate the block of r sums in FP64
-                // (BF16 16x16x32 result layout: lane l, element q -> row 4(l/16) + q, column l%16)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < CT; ++j) {
-                        if (!(mask & (1u << (i * CT + j)))) continue;
-                        const int blk = (row0 + i * 16) >> 4;
-                        double *dst = T + ((size_t)(A.tile_off[t0 + j] + blk) << 8);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            double *d = dst + (4 * zg + q) * 16 + n;
-                            const double v = (double)tot[i][j][q];
-                            *d = first_flush ? v : *d + v;
-                        }
-                        tot[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-                    }
-                first_flush = false;
-            }
+            first_flush = false;
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acur[i] = anext[i];
+        for (int i = 0; i < 4; ++i) {
+            ah[i] = nh[i];
+            al[i] = nl[i];
+        }
         lds_barrier();
     }
 }
