@@ -36,7 +36,8 @@ struct modal_ctx_s {
     Buf ws[NSLOTS];
     size_t limit = 0;
     int next_in = 0;
-    TriplePlan plan64, planmx;         // triple-product plans of the FP64 / mixed kernels
+    TriplePlan plan64;                 // triple-product plan of the FP64 kernel
+    BTPlan planbt;                     // block-triple plan of the mixed kernel
     bool timing = false;
     // per stage: a pool of (start, end) event pairs; the first `used` belong
     // to the last call (chunked stages record one pair per chunk)
@@ -399,13 +400,12 @@ void run_beta(modal_ctx c, const modal_grid *g, const Dims &d, const Grid &G, co
 // rowscale[(l - lrow0) * nk + k] with lrow0 = llo, so the pointer is offset to
 // row llo of delta.
 
-const TriplePlan &ensure_plan(modal_ctx c, int U, modal_precision prec)
+const TriplePlan &ensure_plan64(modal_ctx c, int U)
 {
-    TriplePlan &pl = (prec == MODAL_FP64) ? c->plan64 : c->planmx;
+    TriplePlan &pl = c->plan64;
     if (pl.U == U && pl.tasks) return pl;
     int rb, tpg, gr;
-    if (prec == MODAL_FP64) triple_f64_shape(rb, tpg, gr);
-    else triple_mixed_shape(rb, tpg, gr);
+    triple_f64_shape(rb, tpg, gr);
     std::string err;
     hipck(c, hipStreamSynchronize(c->stream), "sync");
     hipError_t e = build_triple_plan(U, rb, tpg, gr, pl, err);
@@ -413,31 +413,50 @@ const TriplePlan &ensure_plan(modal_ctx c, int U, modal_precision prec)
     return pl;
 }
 
-// Triple products from scaled rows St ([Upad][nr * ldmu]) and gather.
+const BTPlan &ensure_planbt(modal_ctx c, int U)
+{
+    BTPlan &pl = c->planbt;
+    if (pl.U == U && pl.tasks) return pl;
+    std::string err;
+    hipck(c, hipStreamSynchronize(c->stream), "sync");
+    hipError_t e = build_bt_plan(U, pl, err);
+    if (e != hipSuccess) fail(c, e == hipErrorOutOfMemory ? MODAL_ERR_OOM : MODAL_ERR_DEVICE, err);
+    return pl;
+}
+
+// Triple products from the z-blocked scaled rows St ([ldz/32][Upad][32]) and gather.
 void run_triple_gather(modal_ctx c, const modal_problem *p, const Dims &d, modal_precision prec,
                        double *St, double *gamma)
 {
-    const TriplePlan &plan = ensure_plan(c, d.U, prec);
     const int64_t ldz = (int64_t)d.nr * d.ldmu;
-    double *T = (double *)ws_get(c, W_T, sizeof(double) * (size_t)plan.tsize);
-    {
-        StageTimer tm(c, MODAL_STAGE_TRIPLE);
-        if (prec == MODAL_FP64) {
-            hipck(c, launch_triple_f64(plan, pad_to(d.U, kRowPad), ldz, St, T, c->stream), "triple f64");
-        } else {
-            const size_t n = (size_t)pad_to(d.U, kRowPad) * ldz;
-            float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * n);
-            uint16_t *sa = (uint16_t *)ws_get(c, W_SH, 2 * sizeof(uint16_t) * n);
-            hipck(c, launch_split_bf16((int64_t)n, St, s32, sa, c->stream), "split");
-            hipck(c, launch_triple_mixed(plan, pad_to(d.U, kRowPad), ldz, d.nr, d.ldmu, s32, sa, T, c->stream),
-                  "triple mixed");
-        }
-    }
+    const int64_t upad = pad_to(d.U, kRowPad);
     const int *ta = dev_in(c, p->tri_a, (size_t)p->ta * 3);
     const int *tp = dev_in(c, p->tri_p, (size_t)p->tp * 3);
+    if (prec == MODAL_FP64) {
+        const TriplePlan &plan = ensure_plan64(c, d.U);
+        double *T = (double *)ws_get(c, W_T, sizeof(double) * (size_t)plan.tsize);
+        {
+            StageTimer tm(c, MODAL_STAGE_TRIPLE);
+            hipck(c, launch_triple_f64(plan, upad, ldz, St, T, c->stream), "triple f64");
+        }
+        if ((int64_t)p->ta * p->tp == 0) return;
+        StageTimer tm(c, MODAL_STAGE_GATHER);
+        hipck(c, launch_gather(p->kind, p->ta, p->tp, ta, tp, d.np, plan, T, gamma, c->stream), "gather");
+        return;
+    }
+    const BTPlan &plan = ensure_planbt(c, d.U);
+    double *T = (double *)ws_get(c, W_T, sizeof(double) * (size_t)plan.tsize);
+    const size_t n = (size_t)upad * ldz;
+    float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * n);
+    uint16_t *sa = (uint16_t *)ws_get(c, W_SH, 2 * sizeof(uint16_t) * n);
+    {
+        StageTimer tm(c, MODAL_STAGE_TRIPLE);
+        hipck(c, launch_split_bf16((int64_t)n, St, s32, sa, c->stream), "split");
+        hipck(c, launch_triple_bt(plan, upad, ldz, d.ldmu, s32, sa, T, c->stream), "triple mixed");
+    }
     if ((int64_t)p->ta * p->tp == 0) return;
     StageTimer tm(c, MODAL_STAGE_GATHER);
-    hipck(c, launch_gather(p->kind, p->ta, p->tp, ta, tp, d.np, plan, T, gamma, c->stream), "gather");
+    hipck(c, launch_gather_bt(p->kind, p->ta, p->tp, ta, tp, d.np, plan, T, gamma, c->stream), "gather");
 }
 
 }  // namespace
@@ -486,7 +505,7 @@ modal_status modal_destroy(modal_ctx c)
     (void)hipStreamSynchronize(c->stream);
     for (auto &b : c->ws) (void)hipFree(b.p);
     free_triple_plan(c->plan64);
-    free_triple_plan(c->planmx);
+    free_bt_plan(c->planbt);
     for (auto &pool : c->ev)
         for (auto &pr : pool) {
             (void)hipEventDestroy(pr.first);

@@ -112,6 +112,23 @@ hipError_t launch_triple_f64(const TriplePlan &plan, int64_t upad, int64_t ldz,
 hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t upad, int64_t ldz, int nr,
                                int nmu_pad, const float *S32, const uint16_t *SA, double *T,
                                hipStream_t s);
+// Block-triple plan of the mixed kernel: tasks (ib, jb, kb) of 256 x 16 x 16
+// rows, the task index of every block triple (-1 if it holds no i <= j <= k),
+// and T packed per task.
+struct BTPlan {
+    int U = 0;
+    int nib = 0, njb = 0, nkb = 0;
+    int ntasks = 0;
+    int64_t tsize = 0;         // doubles of T
+    int4 *tasks = nullptr;     // device [ntasks]
+    int *tidx = nullptr;       // device [nib][njb][nkb]
+};
+hipError_t build_bt_plan(int U, BTPlan &plan, std::string &err);
+void free_bt_plan(BTPlan &plan);
+hipError_t launch_triple_bt(const BTPlan &plan, int64_t upad, int64_t ldz, int nmu_pad,
+                            const float *S32, const uint16_t *SA, double *T, hipStream_t s);
+hipError_t launch_gather_bt(int kind, int ta, int tp, const int *tri_a, const int *tri_p, int np,
+                            const BTPlan &plan, const double *T, double *gamma, hipStream_t s);
 // Elementwise over the n values (a multiple of 8): FP32 copy and BF16 split.
 hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *SA,
                              hipStream_t s);

@@ -1,0 +1,374 @@
+// Step d, mixed precision: the unique third moments
+//     T[i <= j <= k] = Sum_z St_i(z) St_j(z) St_k(z)
+// of the W^(1/3)-scaled S rows (Eq. (2D); see k_triple.hip for how Gamma is
+// assembled from T) on BF16 matrix cores with split operands.
+//
+// Work decomposition: block triples.  A workgroup task is (ib, jb, kb): the
+// 128 rows i of block ib times the 16 x 16 pairs (j, k) of blocks jb, kb,
+// i.e. 32768 moments.  The column operand St_j(z) St_k(z) of all 256 pairs
+// is generated from only 32 source rows, and the 128 A rows are shared by
+// every task of the same ib; tasks are ordered (ib, jb, kb) and dealt to
+// the XCDs in contiguous runs so that co-resident workgroups read the same A
+// rows through one L2.  Only tasks holding some i <= j <= k are launched;
+// inside one, waves whose 32 rows all exceed the largest j skip the matrix
+// work, and the remaining out-of-order entries are computed but never read.
+//
+// Arithmetic: each value x is split as x = hi + lo with hi the BF16 rounding
+// of x and lo the BF16 rounding of the remainder; a term A B is formed by
+// v_mfma_f32_16x16x32_bf16 as A_lo B_hi + A_hi B_lo + A_hi B_hi (the dropped
+// A_lo B_lo is ~2^-16 of the term).  The A rows are split once in memory;
+// the product operand St_j St_k is formed in FP32 and split per step.  Each
+// r's mu sum accumulates in FP32 in the matrix-core accumulators; when it
+// is complete it is added to the FP64 r sum held in T (each task owns its
+// outputs: a plain read-modify-write, no atomics, deterministic).  The mu
+// sum of an r is always complete before it enters the r sum (Sec. 2.2).
+//
+// Per 32-wide z step and wave: 2 row blocks x 16 pair tiles x 3 products =
+// 96 matrix-core operations; the wave generates 4 of the 16 pair tiles and
+// shares them through LDS (double-buffered, one barrier per step), loads its
+// A fragments directly from memory one step ahead, and stages the 32 source
+// rows of the step after next.
+#include "internal.hpp"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace mp {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int BI = 128, BJ = 16, BK = 16;     // rows per task along i, j, k
+constexpr int RB = BI / 64;                   // 16-row blocks per wave (4 waves)
+constexpr int NT = BJ;                        // pair tiles per task: (j, k0..k0+15)
+constexpr int KZ = 32;                        // z values per step
+constexpr int SRC_ROWS = BJ + BK;             // staged source rows per step
+constexpr int SRC_LD = KZ + 4;                // padded LDS row (floats)
+constexpr int TASK_SIZE = BI * BJ * BK;       // moments per task
+
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);       // lgkmcnt(0) only: global loads stay in flight
+    __builtin_amdgcn_s_barrier();
+}
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ bf8 as_bf8(uint4 v)
+{
+    bf8 r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+
+__device__ __forceinline__ int task_of_block(int bid, int ntasks)
+{
+    const int x = bid & 7, idx = bid >> 3;     // workgroups go to the 8 XCDs round-robin
+    const int base = ntasks >> 3, rem = ntasks & 7;
+    return x * base + (x < rem ? x : rem) + idx;
+}
+
+struct BTArgs {
+    const int4 *tasks;      // (ib, jb, kb, -)
+    int ntasks;
+    int64_t upad;           // rows per z block of the z-blocked S layout
+    int64_t nsteps;         // z steps (nr * nmu_pad / 32)
+    int kpr;                // steps per r
+};
+
+// Offset of moment (i, j, k) inside its task block; the 4 values a lane holds
+// for one matrix-core tile are contiguous.
+__device__ __host__ __forceinline__ int bt_offset(int il, int jl, int kl)
+{
+    const int rb16 = il >> 4, row = il & 15;
+    const int lane = kl + 16 * (row >> 2), q = row & 3;
+    return ((rb16 * NT + jl) * 64 + lane) * 4 + q;
+}
+
+__global__ __launch_bounds__(256) void k_triple_bt(BTArgs A, const float *__restrict__ S32,
+                                                   const uint16_t *__restrict__ SA,
+                                                   double *__restrict__ T)
+{
+    __shared__ float Src[2][SRC_ROWS][SRC_LD];
+    __shared__ uint4 Bb[2][NT][2][64];        // [buf][tile][hi/lo][lane]
+
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int task = task_of_block(blockIdx.x, A.ntasks);
+    const int4 tk = A.tasks[task];
+    const int i0 = tk.x * BI + wave * 16 * RB; // this wave's rows
+    const int j0 = tk.y * BJ, k0 = tk.z * BK;
+    const int n = lane & 15, zg = lane >> 4;
+    const bool active = i0 <= j0 + BJ - 1;     // some row <= some j (wave-uniform)
+
+    f4 acc[RB][NT];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // A fragments of step s: row i0 + 16 i + n, 8-z group zg, at
+    // SA[((s * upad + row) * 4 + zg) * 16]
+    // (32-bit lane offsets from a wave-uniform base keep the addressing in
+    // scalar registers plus one VGPR)
+    const uint32_t aoff = ((uint32_t)(i0 + n) * 4 + zg) << 4;     // uint16 units
+    const size_t astep = (size_t)A.upad << 6;
+    auto aload = [&](int64_t s, uint4 (&h)[RB], uint4 (&l)[RB]) {
+        const uint16_t *base = SA + (size_t)s * astep;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(base + aoff + (uint32_t)(i * 16 * 64));
+            h[i] = p[0];
+            l[i] = p[1];
+        }
+    };
+    // source rows: local 0..15 = j0.., 16..31 = k0..; 32 rows x 8 float4 =
+    // 256 float4, one per thread
+    const int srow = t >> 3, sq = t & 7;
+    const uint32_t soff = ((uint32_t)(srow < BJ ? j0 + srow : k0 + srow - BJ) << 5) + 4 * sq;
+    const size_t sstep = (size_t)A.upad << 5;
+    f4 sreg;
+    auto sload = [&](int64_t s) { sreg = *reinterpret_cast<const f4 *>(S32 + (size_t)s * sstep + soff); };
+    auto sstore = [&](int buf) { *reinterpret_cast<f4 *>(&Src[buf][srow][4 * sq]) = sreg; };
+    // this wave generates pair tiles 4 wave .. 4 wave + 3 (tile = j local)
+    auto bgen_tile = [&](int buf, int q) {
+        const float *pk = &Src[buf][BJ + n][8 * zg];
+        const f4 k0v = *reinterpret_cast<const f4 *>(pk), k1v = *reinterpret_cast<const f4 *>(pk + 4);
+        const int tile = 4 * wave + q;
+        const float *pj = &Src[buf][tile][8 * zg];
+        const f4 j0v = *reinterpret_cast<const f4 *>(pj), j1v = *reinterpret_cast<const f4 *>(pj + 4);
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v[e] = j0v[e] * k0v[e];
+            v[4 + e] = j1v[e] * k1v[e];
+        }
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t h0 = bf16_rne_bits(v[2 * e]), h1 = bf16_rne_bits(v[2 * e + 1]);
+            const float r0 = v[2 * e] - __uint_as_float(h0 << 16);
+            const float r1 = v[2 * e + 1] - __uint_as_float(h1 << 16);
+            h[e] = h0 | (h1 << 16);
+            l[e] = bf16_rne_bits(r0) | (bf16_rne_bits(r1) << 16);
+        }
+        Bb[buf][tile][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
+        Bb[buf][tile][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
+    };
+    auto bgen = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bgen_tile(buf, q);
+    };
+
+    // this wave's output block: tile jl of row block i at
+    // T + task * TASK_SIZE + ((rb16 * NT + jl) * 64 + lane) * 4
+    double *tbase = T + (size_t)task * TASK_SIZE + (size_t)(wave * RB * NT) * 256;
+    const uint32_t toff = (uint32_t)lane * 4;
+
+    const int64_t nsteps = A.nsteps, last = nsteps - 1;
+    uint4 ah[RB], al[RB], nh[RB], nl[RB];
+    sload(0);
+    sstore(0);
+    sload(nsteps > 1 ? 1 : 0);
+    sstore(1);
+    lds_barrier();
+    bgen(0);
+    sload(nsteps > 2 ? 2 : last);
+    aload(0, ah, al);
+    lds_barrier();
+
+    int kin = 0;
+    bool first = true;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int buf = (int)(s & 1);
+        // past the last step these clamp to it; their results are never used
+        aload(s + 1 < last ? s + 1 : last, nh, nl);
+        sstore(buf);                                       // sources of step s + 2
+        sload(s + 3 < last ? s + 3 : last);
+        if (active) {
+            // software pipeline over the 16 pair tiles: the operand of tile
+            // j + 1 is read from LDS while tile j's 12 matrix-core operations
+            // run, and after every fourth tile one of this wave's pair tiles
+            // of step s + 1 is generated (VALU work under the matrix cores).
+            // Scheduling barriers keep at most two tiles' operands live.
+            uint4 bh = Bb[buf][0][0][lane], bl = Bb[buf][0][1][lane];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                uint4 nbh = bh, nbl = bl;
+                if (j + 1 < NT) {
+                    nbh = Bb[buf][j + 1][0][lane];
+                    nbl = Bb[buf][j + 1][1][lane];
+                }
+                const bf8 h8 = as_bf8(bh), l8 = as_bf8(bl);
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), h8, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), l8, acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), h8, acc[i][j], 0, 0, 0);
+                if ((j & 3) == 3) bgen_tile(buf ^ 1, j >> 2);      // operand of step s + 1
+                __builtin_amdgcn_sched_barrier(0);
+                bh = nbh;
+                bl = nbl;
+            }
+        } else {
+            bgen(buf ^ 1);
+        }
+        if (++kin == A.kpr) {
+            // this r's mu sum is complete: add it to the FP64 r sum in T,
+            // eight tiles at a time with their loads issued first
+            kin = 0;
+            if (active) {
+                // opaque copies: without them the compiler hoists all 64 tile
+                // addresses out of the z loop and spills them
+                double *tb = tbase;
+                uint32_t to = toff;
+                asm volatile("" : "+v"(to));
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int jh = 0; jh < NT; jh += 8) {
+                        double2 old[8][2];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const double2 *p = reinterpret_cast<const double2 *>(
+                                tb + to + (uint32_t)((i * NT + jh + j) << 8));
+                            old[j][0] = first ? make_double2(0.0, 0.0) : p[0];
+                            old[j][1] = first ? make_double2(0.0, 0.0) : p[1];
+                        }
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            double2 *p = reinterpret_cast<double2 *>(tb + to + (uint32_t)((i * NT + jh + j) << 8));
+                            const f4 a = acc[i][jh + j];
+                            p[0] = make_double2(old[j][0].x + (double)a[0], old[j][0].y + (double)a[1]);
+                            p[1] = make_double2(old[j][1].x + (double)a[2], old[j][1].y + (double)a[3]);
+                        }
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+            first = false;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            ah[i] = nh[i];
+            al[i] = nl[i];
+        }
+        lds_barrier();
+    }
+}
+
+// ---- gather ---------------------------------------------------------------
+__device__ __forceinline__ double bt_get(int a, int b, int c, const int *__restrict__ tidx, int njb,
+                                         int nkb, const double *__restrict__ T)
+{
+    const int lo = min(a, min(b, c)), hi = max(a, max(b, c));
+    const int mid = a + b + c - lo - hi;
+    const int task = tidx[((lo / BI) * njb + mid / BJ) * nkb + hi / BK];
+    return T[(size_t)task * TASK_SIZE + bt_offset(lo % BI, mid % BJ, hi % BK)];
+}
+
+__global__ void k_gather_bt(int kind, int ta, int tp, const int *__restrict__ tri_a,
+                            const int *__restrict__ tri_p, int np, const int *__restrict__ tidx,
+                            int njb, int nkb, const double *__restrict__ T, double *__restrict__ gamma)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)ta * tp) return;
+    const int n = (int)(e / tp), m = (int)(e % tp);
+    const int a0 = tri_a[3 * n] * np, a1 = tri_a[3 * n + 1] * np, a2 = tri_a[3 * n + 2] * np;
+    const int p0 = tri_p[3 * m], p1 = tri_p[3 * m + 1], p2 = tri_p[3 * m + 2];
+    double v;
+    if (kind == MODAL_GAMMA_ORDERED) {
+        v = bt_get(a0 + p0, a1 + p1, a2 + p2, tidx, njb, nkb, T) * (1.0 / (8.0 * kPi));
+    } else {
+        v = bt_get(a0 + p0, a1 + p1, a2 + p2, tidx, njb, nkb, T) +
+            bt_get(a0 + p0, a1 + p2, a2 + p1, tidx, njb, nkb, T) +
+            bt_get(a0 + p1, a1 + p0, a2 + p2, tidx, njb, nkb, T) +
+            bt_get(a0 + p1, a1 + p2, a2 + p0, tidx, njb, nkb, T) +
+            bt_get(a0 + p2, a1 + p0, a2 + p1, tidx, njb, nkb, T) +
+            bt_get(a0 + p2, a1 + p1, a2 + p0, tidx, njb, nkb, T);
+        v *= 1.0 / (48.0 * kPi);
+    }
+    gamma[e] = v;
+}
+
+}  // namespace
+
+hipError_t build_bt_plan(int U, BTPlan &plan, std::string &err)
+{
+    free_bt_plan(plan);
+    plan.U = U;
+    plan.nib = (U + BI - 1) / BI;
+    plan.njb = (U + BJ - 1) / BJ;
+    plan.nkb = (U + BK - 1) / BK;
+    std::vector<int> tidx((size_t)plan.nib * plan.njb * plan.nkb, -1);
+    std::vector<int4> tasks;
+    for (int ib = 0; ib < plan.nib; ++ib)
+        for (int jb = 0; jb < plan.njb; ++jb) {
+            const int jmax = std::min(jb * BJ + BJ - 1, U - 1);
+            if (ib * BI > jmax) continue;
+            for (int kb = 0; kb < plan.nkb; ++kb) {
+                if (jb * BJ > kb * BK + BK - 1) continue;
+                tidx[((size_t)ib * plan.njb + jb) * plan.nkb + kb] = (int)tasks.size();
+                tasks.push_back(make_int4(ib, jb, kb, 0));
+            }
+        }
+    plan.ntasks = (int)tasks.size();
+    plan.tsize = (int64_t)plan.ntasks * TASK_SIZE;
+    hipError_t e = hipMalloc((void **)&plan.tasks, sizeof(int4) * std::max<size_t>(tasks.size(), 1));
+    if (e == hipSuccess && !tasks.empty())
+        e = hipMemcpy(plan.tasks, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void **)&plan.tidx, sizeof(int) * tidx.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(plan.tidx, tidx.data(), sizeof(int) * tidx.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        err = std::string("block-triple plan upload: ") + hipGetErrorString(e);
+        free_bt_plan(plan);
+    }
+    return e;
+}
+
+void free_bt_plan(BTPlan &p)
+{
+    (void)hipFree(p.tasks);
+    (void)hipFree(p.tidx);
+    p = BTPlan{};
+}
+
+hipError_t launch_triple_bt(const BTPlan &plan, int64_t upad, int64_t ldz, int nmu_pad,
+                            const float *S32, const uint16_t *SA, double *T, hipStream_t s)
+{
+    if (nmu_pad % KZ != 0 || ldz % nmu_pad != 0 || upad % BI != 0 || upad < plan.U)
+        return hipErrorInvalidValue;
+    if (plan.ntasks == 0) return hipSuccess;
+    BTArgs a;
+    a.tasks = plan.tasks;
+    a.ntasks = plan.ntasks;
+    a.upad = upad;
+    a.nsteps = ldz / KZ;
+    a.kpr = nmu_pad / KZ;
+    hipLaunchKernelGGL(k_triple_bt, dim3(plan.ntasks), dim3(256), 0, s, a, S32, SA, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_bt(int kind, int ta, int tp, const int *tri_a, const int *tri_p, int np,
+                            const BTPlan &plan, const double *T, double *gamma, hipStream_t s)
+{
+    const int64_t n = (int64_t)ta * tp;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_bt, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, kind, ta, tp,
+                       tri_a, tri_p, np, plan.tidx, plan.njb, plan.nkb, T, gamma);
+    return hipGetLastError();
+}
+
+}  // namespace mp
