@@ -23,11 +23,13 @@
 // outputs: a plain read-modify-write, no atomics, deterministic).  The mu
 // sum of an r is always complete before it enters the r sum (Sec. 2.2).
 //
-// Per 32-wide z step and wave: 2 row blocks x 16 pair tiles x 3 products =
-// 96 matrix-core operations; the wave generates 4 of the 16 pair tiles and
-// shares them through LDS (double-buffered, one barrier per step), loads its
-// A fragments directly from memory one step ahead, and stages the 32 source
-// rows of the step after next.
+// Eight waves (two per SIMD): wave w owns rows 32 (w % 4) .. + 31 of the
+// task and pair tiles 8 (w / 4) .. + 7.  Per 32-wide z step a wave issues
+// 2 row blocks x 8 pair tiles x 3 products = 48 matrix-core operations,
+// generates 2 of the 16 pair tiles for the next step and shares them through
+// LDS (double-buffered, one barrier per step), loads its A fragments straight
+// from memory, and the first four waves stage the 32 source rows of the step
+// after next.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -40,7 +42,8 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int BI = 128, BJ = 16, BK = 16;     // rows per task along i, j, k
-constexpr int RB = BI / 64;                   // 16-row blocks per wave (4 waves)
+constexpr int RB = 2;                         // 16-row blocks per wave
+constexpr int TW = 8;                         // pair tiles per wave
 constexpr int NT = BJ;                        // pair tiles per task: (j, k0..k0+15)
 constexpr int KZ = 32;                        // z values per step
 constexpr int SRC_ROWS = BJ + BK;             // staged source rows per step
@@ -90,7 +93,7 @@ __device__ __host__ __forceinline__ int bt_offset(int il, int jl, int kl)
     return ((rb16 * NT + jl) * 64 + lane) * 4 + q;
 }
 
-__global__ __launch_bounds__(256) void k_triple_bt(BTArgs A, const float *__restrict__ S32,
+__global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__restrict__ S32,
                                                    const uint16_t *__restrict__ SA,
                                                    double *__restrict__ T)
 {
@@ -99,47 +102,53 @@ __global__ __launch_bounds__(256) void k_triple_bt(BTArgs A, const float *__rest
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int rg = wave & 3, th = wave >> 2;   // row group (32 rows), tile half (8 tiles)
     const int task = task_of_block(blockIdx.x, A.ntasks);
     const int4 tk = A.tasks[task];
-    const int i0 = tk.x * BI + wave * 16 * RB; // this wave's rows
+    const int i0 = tk.x * BI + rg * 16 * RB;   // this wave's rows
     const int j0 = tk.y * BJ, k0 = tk.z * BK;
     const int n = lane & 15, zg = lane >> 4;
     const bool active = i0 <= j0 + BJ - 1;     // some row <= some j (wave-uniform)
 
-    f4 acc[RB][NT];
+    f4 acc[RB][TW];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
     // A fragments of step s: row i0 + 16 i + n, 8-z group zg, at
-    // SA[((s * upad + row) * 4 + zg) * 16]
-    // (32-bit lane offsets from a wave-uniform base keep the addressing in
-    // scalar registers plus one VGPR)
+    // SA[((s * upad + row) * 4 + zg) * 16]; 32-bit lane offsets from a
+    // wave-uniform base keep the addressing in scalar registers plus one VGPR
     const uint32_t aoff = ((uint32_t)(i0 + n) * 4 + zg) << 4;     // uint16 units
     const size_t astep = (size_t)A.upad << 6;
-    auto aload = [&](int64_t s, uint4 (&h)[RB], uint4 (&l)[RB]) {
+    uint4 ah[RB], al[RB];
+    auto aload = [&](int64_t s) {
         const uint16_t *base = SA + (size_t)s * astep;
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
             const uint4 *p = reinterpret_cast<const uint4 *>(base + aoff + (uint32_t)(i * 16 * 64));
-            h[i] = p[0];
-            l[i] = p[1];
+            ah[i] = p[0];
+            al[i] = p[1];
         }
     };
     // source rows: local 0..15 = j0.., 16..31 = k0..; 32 rows x 8 float4 =
-    // 256 float4, one per thread
-    const int srow = t >> 3, sq = t & 7;
+    // 256 float4, staged by the first four waves
+    const bool stager = t < 256;
+    const int srow = (t & 255) >> 3, sq = t & 7;
     const uint32_t soff = ((uint32_t)(srow < BJ ? j0 + srow : k0 + srow - BJ) << 5) + 4 * sq;
     const size_t sstep = (size_t)A.upad << 5;
-    f4 sreg;
-    auto sload = [&](int64_t s) { sreg = *reinterpret_cast<const f4 *>(S32 + (size_t)s * sstep + soff); };
-    auto sstore = [&](int buf) { *reinterpret_cast<f4 *>(&Src[buf][srow][4 * sq]) = sreg; };
-    // this wave generates pair tiles 4 wave .. 4 wave + 3 (tile = j local)
+    f4 sreg = f4{0.f, 0.f, 0.f, 0.f};
+    auto sload = [&](int64_t s) {
+        if (stager) sreg = *reinterpret_cast<const f4 *>(S32 + (size_t)s * sstep + soff);
+    };
+    auto sstore = [&](int buf) {
+        if (stager) *reinterpret_cast<f4 *>(&Src[buf][srow][4 * sq]) = sreg;
+    };
+    // this wave generates pair tiles 2 wave and 2 wave + 1 (tile = j local)
     auto bgen_tile = [&](int buf, int q) {
         const float *pk = &Src[buf][BJ + n][8 * zg];
         const f4 k0v = *reinterpret_cast<const f4 *>(pk), k1v = *reinterpret_cast<const f4 *>(pk + 4);
-        const int tile = 4 * wave + q;
+        const int tile = 2 * wave + q;
         const float *pj = &Src[buf][tile][8 * zg];
         const f4 j0v = *reinterpret_cast<const f4 *>(pj), j1v = *reinterpret_cast<const f4 *>(pj + 4);
         float v[8];
@@ -160,26 +169,22 @@ __global__ __launch_bounds__(256) void k_triple_bt(BTArgs A, const float *__rest
         Bb[buf][tile][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
         Bb[buf][tile][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
     };
-    auto bgen = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bgen_tile(buf, q);
-    };
 
-    // this wave's output block: tile jl of row block i at
+    // this wave's output: tile jl = TW th + j of row block rb16 = RB rg + i at
     // T + task * TASK_SIZE + ((rb16 * NT + jl) * 64 + lane) * 4
-    double *tbase = T + (size_t)task * TASK_SIZE + (size_t)(wave * RB * NT) * 256;
+    double *tbase = T + (size_t)task * TASK_SIZE + (size_t)(rg * RB * NT + th * TW) * 256;
     const uint32_t toff = (uint32_t)lane * 4;
 
     const int64_t nsteps = A.nsteps, last = nsteps - 1;
-    uint4 ah[RB], al[RB], nh[RB], nl[RB];
     sload(0);
     sstore(0);
     sload(nsteps > 1 ? 1 : 0);
     sstore(1);
     lds_barrier();
-    bgen(0);
+    bgen_tile(0, 0);
+    bgen_tile(0, 1);
     sload(nsteps > 2 ? 2 : last);
-    aload(0, ah, al);
+    aload(0);
     lds_barrier();
 
     int kin = 0;
@@ -187,22 +192,20 @@ __global__ __launch_bounds__(256) void k_triple_bt(BTArgs A, const float *__rest
     for (int64_t s = 0; s < nsteps; ++s) {
         const int buf = (int)(s & 1);
         // past the last step these clamp to it; their results are never used
-        aload(s + 1 < last ? s + 1 : last, nh, nl);
         sstore(buf);                                       // sources of step s + 2
         sload(s + 3 < last ? s + 3 : last);
         if (active) {
-            // software pipeline over the 16 pair tiles: the operand of tile
-            // j + 1 is read from LDS while tile j's 12 matrix-core operations
-            // run, and after every fourth tile one of this wave's pair tiles
-            // of step s + 1 is generated (VALU work under the matrix cores).
-            // Scheduling barriers keep at most two tiles' operands live.
-            uint4 bh = Bb[buf][0][0][lane], bl = Bb[buf][0][1][lane];
+            // software pipeline over this wave's 8 pair tiles: the operand of
+            // tile j + 1 is read from LDS while tile j's 6 matrix-core
+            // operations run; this wave's 2 pair tiles of step s + 1 are
+            // generated after tiles 3 and 7 (VALU work under the matrix cores)
+            uint4 bh = Bb[buf][th * TW][0][lane], bl = Bb[buf][th * TW][1][lane];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
+            for (int j = 0; j < TW; ++j) {
                 uint4 nbh = bh, nbl = bl;
-                if (j + 1 < NT) {
-                    nbh = Bb[buf][j + 1][0][lane];
-                    nbl = Bb[buf][j + 1][1][lane];
+                if (j + 1 < TW) {
+                    nbh = Bb[buf][th * TW + j + 1][0][lane];
+                    nbl = Bb[buf][th * TW + j + 1][1][lane];
                 }
                 const bf8 h8 = as_bf8(bh), l8 = as_bf8(bl);
 #pragma unroll
@@ -220,33 +223,33 @@ __global__ __launch_bounds__(256) void k_triple_bt(BTArgs A, const float *__rest
                 bl = nbl;
             }
         } else {
-            bgen(buf ^ 1);
+            bgen_tile(buf ^ 1, 0);
+            bgen_tile(buf ^ 1, 1);
         }
         if (++kin == A.kpr) {
             // this r's mu sum is complete: add it to the FP64 r sum in T,
-            // eight tiles at a time with their loads issued first
+            // four tiles at a time with their loads issued first
             kin = 0;
             if (active) {
-                // opaque copies: without them the compiler hoists all 64 tile
-                // addresses out of the z loop and spills them
-                double *tb = tbase;
+                // opaque copy: keeps the compiler from hoisting every tile
+                // address out of the z loop
                 uint32_t to = toff;
                 asm volatile("" : "+v"(to));
 #pragma unroll
                 for (int i = 0; i < RB; ++i)
 #pragma unroll
-                    for (int jh = 0; jh < NT; jh += 8) {
-                        double2 old[8][2];
+                    for (int jh = 0; jh < TW; jh += 4) {
+                        double2 old[4][2];
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) {
+                        for (int j = 0; j < 4; ++j) {
                             const double2 *p = reinterpret_cast<const double2 *>(
-                                tb + to + (uint32_t)((i * NT + jh + j) << 8));
+                                tbase + to + (uint32_t)((i * NT + jh + j) << 8));
                             old[j][0] = first ? make_double2(0.0, 0.0) : p[0];
                             old[j][1] = first ? make_double2(0.0, 0.0) : p[1];
                         }
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            double2 *p = reinterpret_cast<double2 *>(tb + to + (uint32_t)((i * NT + jh + j) << 8));
+                        for (int j = 0; j < 4; ++j) {
+                            double2 *p = reinterpret_cast<double2 *>(tbase + to + (uint32_t)((i * NT + jh + j) << 8));
                             const f4 a = acc[i][jh + j];
                             p[0] = make_double2(old[j][0].x + (double)a[0], old[j][0].y + (double)a[1]);
                             p[1] = make_double2(old[j][1].x + (double)a[2], old[j][1].y + (double)a[3]);
@@ -256,14 +259,11 @@ __global__ __launch_bounds__(256) void k_triple_bt(BTArgs A, const float *__rest
 #pragma unroll
             for (int i = 0; i < RB; ++i)
 #pragma unroll
-                for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+                for (int j = 0; j < TW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
             first = false;
         }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            ah[i] = nh[i];
-            al[i] = nl[i];
-        }
+        // A fragments of step s + 1 (the other wave of the SIMD covers the latency)
+        aload(s + 1 < last ? s + 1 : last);
         lds_barrier();
     }
 }
@@ -357,7 +357,7 @@ hipError_t launch_triple_bt(const BTPlan &plan, int64_t upad, int64_t ldz, int n
     a.upad = upad;
     a.nsteps = ldz / KZ;
     a.kpr = nmu_pad / KZ;
-    hipLaunchKernelGGL(k_triple_bt, dim3(plan.ntasks), dim3(256), 0, s, a, S32, SA, T);
+    hipLaunchKernelGGL(k_triple_bt, dim3(plan.ntasks), dim3(512), 0, s, a, S32, SA, T);
     return hipGetLastError();
 }
 
