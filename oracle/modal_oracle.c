@@ -17,6 +17,11 @@
  *                             the mu integral is done before the r integral
  *   Sec. 3.2.3                trapezium rule for the r integral (weights are inputs here)
  *
+ * The adjoint routines (gradient of a scalar loss of Gamma with respect to
+ * the primordial basis q_p(k) and the transfer table Delta_l(k)) differentiate
+ * the same definitions stage by stage, in reverse order: Gamma -> S -> beta
+ * -> (q, Delta).
+ *
  * Names in this file: S_ap(r,mu) is the paper's P_ii'(r,mu) with a <-> i
  * (late-time mode) and p <-> i' (primordial mode); beta_p(l,r) is the
  * paper's projected mode qt_p(r,l), carrying an extra 2/pi.
@@ -312,6 +317,148 @@ int or_gamma_entries(int kind, int nr, const double *r, const double *wr,
         gamma[e] = c * outer;
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of the Gamma entries with respect to S (Eq. (2D)            */
+/* differentiated).  g[e] = dL/dGamma_e.  Shat has S's shape and is    */
+/* overwritten with dL/dS = Sum_e g_e dGamma_e/dS:                     */
+/*   ordered:   F = S00 S11 S22, dF/dS_ss = product of the other two   */
+/*   symmetric: F = permanent, dF/dS_st = permanent of the 2x2 minor   */
+/* each weighted by c wr_r r^2 wmu_mu.  Each thread owns one r.        */
+/* ------------------------------------------------------------------ */
+int or_gamma_adjoint(int kind, int nr, const double *r, const double *wr,
+                     int nmu, const double *wmu, int nS, const double *S,
+                     int64_t ne, const int32_t *sidx, const double *g, double *Shat)
+{
+    for (int64_t e = 0; e < 9 * ne; ++e) if (sidx[e] < 0 || sidx[e] >= nS) return -1;
+    double c = (kind == 0) ? 1.0 / (8.0 * OR_PI) : 1.0 / (48.0 * OR_PI);
+    memset(Shat, 0, sizeof(double) * (size_t)nS * nr * nmu);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < nr; ++q) {
+        double wq = c * wr[q] * r[q] * r[q];
+        for (int64_t e = 0; e < ne; ++e) {
+            const int32_t *ix = sidx + 9 * e;
+            for (int j = 0; j < nmu; ++j) {
+                double m[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        m[a][b] = S[((size_t)ix[3 * a + b] * nr + q) * nmu + j];
+                double w = wq * wmu[j] * g[e];
+                if (kind == 0) {
+                    Shat[((size_t)ix[0] * nr + q) * nmu + j] += w * m[1][1] * m[2][2];
+                    Shat[((size_t)ix[4] * nr + q) * nmu + j] += w * m[0][0] * m[2][2];
+                    Shat[((size_t)ix[8] * nr + q) * nmu + j] += w * m[0][0] * m[1][1];
+                } else {
+                    for (int a = 0; a < 3; ++a) {
+                        int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+                        for (int b = 0; b < 3; ++b) {
+                            int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+                            double minor = m[a1][b1] * m[a2][b2] + m[a1][b2] * m[a2][b1];
+                            Shat[((size_t)ix[3 * a + b] * nr + q) * nmu + j] += w * minor;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of S with respect to beta (Eq. (legendre) is linear in       */
+/* beta): bhat[b][l - lmin][r] = Sum over pairs s with pairs[2s+1] = b  */
+/* of Sum_mu Shat[s][r][mu] w_l qbar_a(l) P_l(mu), a = pairs[2s].       */
+/* ------------------------------------------------------------------ */
+int or_S_adjoint(int lmin, int lmax, const double *cl, double v_power, int na, const double *ql,
+                 int nr, int nmu, const double *P, int nb, int npairs, const int32_t *pairs,
+                 const double *Shat, double *bhat)
+{
+    int L = lmax - lmin + 1;
+    for (int s = 0; s < npairs; ++s) {
+        if (pairs[2 * s] < 0 || pairs[2 * s] >= na) return -1;
+        if (pairs[2 * s + 1] < 0 || pairs[2 * s + 1] >= nb) return -1;
+    }
+    for (int l = 0; l < L; ++l) if (!(cl[l] > 0.0)) return -3;
+    double *wl = (double *)malloc(sizeof(double) * (size_t)L);
+    if (!wl) return -2;
+    for (int l = lmin; l <= lmax; ++l)
+        wl[l - lmin] = pow(2.0 * l + 1.0, 1.0 - v_power) / sqrt(cl[l - lmin]);
+    memset(bhat, 0, sizeof(double) * (size_t)nb * L * nr);
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (int b = 0; b < nb; ++b) {
+        for (int l = lmin; l <= lmax; ++l) {
+            for (int q = 0; q < nr; ++q) {
+                double acc = 0.0;
+                for (int s = 0; s < npairs; ++s) {
+                    if (pairs[2 * s + 1] != b) continue;
+                    int a = pairs[2 * s];
+                    double inner = 0.0;
+                    for (int j = 0; j < nmu; ++j)
+                        inner += Shat[((size_t)s * nr + q) * nmu + j] * P[(size_t)j * (lmax + 1) + l];
+                    acc += wl[l - lmin] * ql[(size_t)a * L + (l - lmin)] * inner;
+                }
+                bhat[((size_t)b * L + (l - lmin)) * nr + q] = acc;
+            }
+        }
+    }
+    free(wl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of beta (Appendix, projected modes, times 2/pi): with       */
+/* Ahat_l[p][k] = Sum_r bhat[p][l][r] j_l(k r),                        */
+/*   dq[p][k]      = Sum_l (2/pi) wk k^2 Delta_l(k) Ahat_l[p][k]       */
+/*   ddelta[l][k]  = Sum_p (2/pi) wk k^2 q_p(k)     Ahat_l[p][k]       */
+/* bhat holds every primordial mode p < np.  Each thread owns a k.     */
+/* ------------------------------------------------------------------ */
+int or_beta_adjoint(int lmin, int lmax, int nk, const double *k, const double *wk,
+                    int nr, const double *r, int np, const double *qk, const double *delta,
+                    const double *bhat, double *dq, double *ddelta)
+{
+    int L = lmax - lmin + 1;
+    double xmax = 0.0;
+    for (int i = 0; i < nk; ++i) for (int q = 0; q < nr; ++q)
+        if (k[i] * r[q] > xmax) xmax = k[i] * r[q];
+    int topmax = (int)ceil(xmax + 20.0 * cbrt(xmax) + 50.0) + lmax + 4;
+    int bad = 0;
+    #pragma omp parallel
+    {
+        double *jl = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        double *work = (double *)malloc(sizeof(double) * (size_t)(topmax + 2));
+        double *Ah = (double *)malloc(sizeof(double) * (size_t)np * L);
+        if (!jl || !work || !Ah) {
+            #pragma omp atomic write
+            bad = 1;
+        } else {
+            #pragma omp for schedule(dynamic, 4)
+            for (int i = 0; i < nk; ++i) {
+                memset(Ah, 0, sizeof(double) * (size_t)np * L);
+                for (int q = 0; q < nr; ++q) {
+                    or_sph_bessel_one(lmax, k[i] * r[q], jl, work);
+                    for (int p = 0; p < np; ++p)
+                        for (int l = lmin; l <= lmax; ++l)
+                            Ah[(size_t)p * L + (l - lmin)] += bhat[((size_t)p * L + (l - lmin)) * nr + q] * jl[l];
+                }
+                double base = 2.0 / OR_PI * wk[i] * k[i] * k[i];
+                for (int p = 0; p < np; ++p) {
+                    double acc = 0.0;
+                    for (int l = 0; l < L; ++l) acc += delta[(size_t)l * nk + i] * Ah[(size_t)p * L + l];
+                    dq[(size_t)p * nk + i] = base * acc;
+                }
+                for (int l = 0; l < L; ++l) {
+                    double acc = 0.0;
+                    for (int p = 0; p < np; ++p) acc += qk[(size_t)p * nk + i] * Ah[(size_t)p * L + l];
+                    ddelta[(size_t)l * nk + i] = base * acc;
+                }
+            }
+        }
+        free(jl);
+        free(work);
+        free(Ah);
+    }
+    return bad ? -2 : 0;
 }
 
 int or_num_threads(void)

@@ -53,6 +53,13 @@ def lib():
                            ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_int, _ip, _dp]
         L.or_gamma_entries.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
                                        ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp]
+        L.or_gamma_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
+                                       ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp, _dp]
+        L.or_S_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int,
+                                   _dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                   _ip, _dp, _dp]
+        L.or_beta_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                      ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         L.or_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -214,6 +221,74 @@ def full_S(inp, mu):
     bet = beta(inp)
     pairs = np.array([(a, p) for a in range(na) for p in range(npm)], dtype=np.int32)
     return S_pairs(inp, mu, bet, pairs).reshape(na, npm, inp.cfg.nr, len(mu)), bet
+
+
+# ------------------------------------------------- adjoint (gradient of a scalar loss)
+def gamma_adjoint_S(inp, wmu, S_arr, sidx, g) -> np.ndarray:
+    """dL/dS for the S stack S_arr given dL/dGamma_e = g[e] of the entries
+    described by sidx (as in gamma_from_S)."""
+    c = inp.cfg
+    S_arr, sp_ = _d(S_arr)
+    sidx, sip = _i(np.asarray(sidx).reshape(-1, 9))
+    g, gp = _d(np.asarray(g, dtype=np.float64).ravel())
+    r, rp = _d(inp.r)
+    wr, wrp = _d(inp.wr)
+    wmu, wmp = _d(wmu)
+    out = np.empty_like(S_arr)
+    _check(lib().or_gamma_adjoint(_kind_code(c.kind), c.nr, rp, wrp, wmu.size, wmp,
+                                  S_arr.shape[0], sp_, sidx.shape[0], sip, gp,
+                                  out.ctypes.data_as(_dp)), "gamma adjoint")
+    return out
+
+
+def S_adjoint(inp, mu, Shat, pairs, nb) -> np.ndarray:
+    """dL/dbeta[b][l][r] from dL/dS of the given (a, b) pairs."""
+    c = inp.cfg
+    P = legendre_table(c.lmax, mu)
+    pairs, pr = _i(np.asarray(pairs).reshape(-1, 2))
+    cl, clp = _d(inp.cl)
+    ql, qlp = _d(inp.ql)
+    Sh, shp = _d(Shat)
+    Pm, Pp = _d(P)
+    out = np.empty((nb, c.L, c.nr))
+    _check(lib().or_S_adjoint(c.lmin, c.lmax, clp, c.v_power, ql.shape[0], qlp, c.nr, len(mu),
+                              Pp, nb, pairs.shape[0], pr, shp, out.ctypes.data_as(_dp)),
+           "S adjoint")
+    return out
+
+
+def beta_adjoint(inp, bhat):
+    """(dL/dq [np][nk], dL/dDelta [L][nk]) from dL/dbeta [np][L][nr]."""
+    c = inp.cfg
+    k, kp = _d(inp.k)
+    wk, wkp = _d(inp.wk)
+    r, rp = _d(inp.r)
+    qk, qp = _d(inp.qk)
+    de, dp = _d(inp.delta)
+    bh, bhp = _d(bhat)
+    dq = np.empty_like(qk)
+    dd = np.empty_like(de)
+    _check(lib().or_beta_adjoint(c.lmin, c.lmax, k.size, kp, wkp, r.size, rp, qk.shape[0], qp, dp,
+                                 bhp, dq.ctypes.data_as(_dp), dd.ctypes.data_as(_dp)),
+           "beta adjoint")
+    return dq, dd
+
+
+def gamma_full_backward(inp, dG, mu=None, wmu=None):
+    """Gradient of L with dL/dGamma = dG (shape [ta][tp]) with respect to
+    q_p(k) and Delta_l(k): the stage adjoints applied in reverse order."""
+    c = inp.cfg
+    if mu is None:
+        mu, wmu = gauss_legendre(c.nmu)
+    na, npm = inp.ql.shape[0], inp.qk.shape[0]
+    bet = beta(inp)
+    pairs = np.array([(a, p) for a in range(na) for p in range(npm)], dtype=np.int32)
+    S_arr = S_pairs(inp, mu, bet, pairs)
+    ta, tp = inp.tri_a, inp.tri_p
+    sidx = (ta[:, None, :, None] * npm + tp[None, :, None, :]).reshape(-1, 9)
+    Shat = gamma_adjoint_S(inp, wmu, S_arr, sidx, np.asarray(dG).ravel())
+    bhat = S_adjoint(inp, mu, Shat, pairs, npm)
+    return beta_adjoint(inp, bhat)
 
 
 # ------------------------------------------------- exact 3j and brute force
