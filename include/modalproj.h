@@ -145,10 +145,12 @@ modal_status modal_workspace_bytes(modal_ctx ctx, const modal_grid *grid,
 /* Stage timing.  When enabled, each later call records HIP events around
  * its kernels on the context's stream; modal_stage_times then waits for the
  * stream and reports the milliseconds of the last call's stages, in order
- * MODAL_STAGE_GL, _LEGENDRE, _BESSEL, _BETA, _S, _TRIPLE, _GATHER (0 for a
- * stage the call did not run).  n is the length of ms (>= MODAL_NSTAGES). */
+ * MODAL_STAGE_GL, _LEGENDRE, _BESSEL, _BETA, _S, _TRIPLE, _GATHER and the
+ * adjoint's _ADJ_TRIPLE, _ADJ_S, _ADJ_BETA (0 for a stage the call did not
+ * run).  n is the length of ms (>= MODAL_NSTAGES). */
 enum { MODAL_STAGE_GL = 0, MODAL_STAGE_LEGENDRE, MODAL_STAGE_BESSEL, MODAL_STAGE_BETA,
-       MODAL_STAGE_S, MODAL_STAGE_TRIPLE, MODAL_STAGE_GATHER, MODAL_NSTAGES };
+       MODAL_STAGE_S, MODAL_STAGE_TRIPLE, MODAL_STAGE_GATHER,
+       MODAL_STAGE_ADJ_TRIPLE, MODAL_STAGE_ADJ_S, MODAL_STAGE_ADJ_BETA, MODAL_NSTAGES };
 modal_status modal_enable_timing(modal_ctx ctx, int on);
 modal_status modal_stage_times(modal_ctx ctx, double *ms, int n);
 
@@ -196,6 +198,19 @@ modal_status modal_gamma_from_S(modal_ctx ctx, const modal_grid *grid,
  * gamma: [ta][tp]. */
 modal_status modal_gamma(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
                          modal_precision prec, double *gamma);
+
+/* Gradient of a scalar loss L of Gamma (the adjoint of modal_gamma, with the
+ * same grid and problem): given dgamma = dL/dGamma ([ta][tp]), writes
+ * dqk = dL/dq_p(k) ([np][nk]) and ddelta = dL/dDelta_l(k) ([L][nk]); either
+ * output may be NULL.  Every stage of the forward (Eq. (2D), Eq. (legendre),
+ * the Appendix's projected modes) is differentiated in reverse order; the
+ * j_l tables are regenerated, never stored.  The mode lists must not repeat a
+ * triple (for SYMMETRIC: a sorted triple), else MODAL_ERR_SHAPE.  Both
+ * precisions run the adjoint stages in FP64 in this version, and np * na
+ * must be at most 512 (else MODAL_ERR_UNSUPPORTED). */
+modal_status modal_gamma_backward(modal_ctx ctx, const modal_grid *grid,
+                                  const modal_problem *prob, modal_precision prec,
+                                  const double *dgamma, double *dqk, double *ddelta);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,9 @@ thread_local std::string g_last_error;   // for calls without a usable context
 
 enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
-    W_S32, W_SH, W_SL, W_GAMMA, W_IN0, NSLOTS = W_IN0 + 16
+    W_S32, W_SH, W_SL, W_GAMMA,
+    W_INVA, W_INVP, W_H, W_SHAT, W_Y, W_BHAT, W_AHAT, W_DQ, W_DD,
+    W_IN0, NSLOTS = W_IN0 + 16
 };
 
 struct Buf {
@@ -400,6 +402,51 @@ void run_beta(modal_ctx c, const modal_grid *g, const Dims &d, const Grid &G, co
 // rowscale[(l - lrow0) * nk + k] with lrow0 = llo, so the pointer is offset to
 // row llo of delta.
 
+// Steps a-c of the forward projection: GL rule, Legendre table, weights,
+// beta (Bessel chunks) and the scaled, z-blocked S rows.
+struct Forward {
+    Grid G;
+    const double *delta, *qk, *cl, *ql;
+    double *P, *wl, *wz, *beta, *St;
+};
+
+Forward run_forward(modal_ctx c, const modal_grid *g, const modal_problem *p, const Dims &d)
+{
+    Forward f;
+    f.G = stage_grid(c, g, d);
+    f.delta = dev_in(c, p->delta, (size_t)d.L * d.nk);
+    f.qk = dev_in(c, p->qk, (size_t)d.np * d.nk);
+    f.cl = dev_in(c, p->cl, (size_t)d.L);
+    f.ql = dev_in(c, p->ql, (size_t)d.na * d.L);
+    // (a) Legendre table at the nodes, weights
+    f.P = (double *)ws_get(c, W_P, sizeof(double) * (size_t)d.L * d.ldmu);
+    f.wl = (double *)ws_get(c, W_WL, sizeof(double) * d.L);
+    const int64_t ldz = (int64_t)d.nr * d.ldmu;
+    f.wz = (double *)ws_get(c, W_WZ, sizeof(double) * ldz);
+    {
+        StageTimer tm(c, MODAL_STAGE_LEGENDRE);
+        hipck(c, launch_legendre_table(g->lmax, g->lmin, d.nmu, d.ldmu, f.G.mu, f.P, c->stream), "legendre");
+    }
+    // (a, b) Bessel functions and the k contraction
+    f.beta = (double *)ws_get(c, W_BETA, sizeof(double) * (size_t)d.np * d.L * d.nr);
+    run_beta(c, g, d, f.G, f.delta, f.qk, f.beta);
+    // (c) the l contraction, scaled rows
+    const int Upad = pad_to(d.U, kRowPad);
+    f.St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * ldz);
+    {
+        StageTimer tm(c, MODAL_STAGE_S);
+        hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, f.cl, f.wl, c->stream), "weights");
+        hipck(c, launch_cbrt_weights(d.nr, d.nmu, d.ldmu, f.G.r, f.G.wr, f.G.wmu, f.wz, c->stream),
+              "cbrt weights");
+        // the padding rows U..Upad of every z block must read as zero
+        zero_pad_rows(c, f.St, ldz, Upad, d.U);
+        hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.ldmu, d.L, f.wl, f.ql, f.beta, f.P, d.ldmu, f.wz, Upad,
+                               f.St, c->stream),
+              "S gemm");
+    }
+    return f;
+}
+
 const TriplePlan &ensure_plan64(modal_ctx c, int U)
 {
     TriplePlan &pl = c->plan64;
@@ -739,41 +786,122 @@ modal_status modal_gamma(modal_ctx c, const modal_grid *g, const modal_problem *
         Dims d = check_grid(c, g, true);
         check_problem(c, p, d, true, true);
         need(c, gamma != nullptr || (int64_t)p->ta * p->tp == 0, MODAL_ERR_INVALID_ARG, "gamma is NULL");
-        Grid G = stage_grid(c, g, d);
-        const double *delta = dev_in(c, p->delta, (size_t)d.L * d.nk);
-        const double *qk = dev_in(c, p->qk, (size_t)d.np * d.nk);
-        const double *cl = dev_in(c, p->cl, (size_t)d.L);
-        const double *ql = dev_in(c, p->ql, (size_t)d.na * d.L);
         OutBuf o = dev_out(c, gamma, (size_t)p->ta * p->tp, W_GAMMA);
-
-        // (a) Legendre table at the nodes, weights
-        double *P = (double *)ws_get(c, W_P, sizeof(double) * (size_t)d.L * d.ldmu);
-        double *wl = (double *)ws_get(c, W_WL, sizeof(double) * d.L);
-        const int64_t ldz = (int64_t)d.nr * d.ldmu;
-        double *wz = (double *)ws_get(c, W_WZ, sizeof(double) * ldz);
-        {
-            StageTimer tm(c, MODAL_STAGE_LEGENDRE);
-            hipck(c, launch_legendre_table(g->lmax, g->lmin, d.nmu, d.ldmu, G.mu, P, c->stream), "legendre");
-        }
-        // (a, b) Bessel functions and the k contraction
-        double *beta = (double *)ws_get(c, W_BETA, sizeof(double) * (size_t)d.np * d.L * d.nr);
-        run_beta(c, g, d, G, delta, qk, beta);
-        // (c) the l contraction, scaled rows
-        const int Upad = pad_to(d.U, kRowPad);
-        double *St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * ldz);
-        {
-            StageTimer tm(c, MODAL_STAGE_S);
-            hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, cl, wl, c->stream), "weights");
-            hipck(c, launch_cbrt_weights(d.nr, d.nmu, d.ldmu, G.r, G.wr, G.wmu, wz, c->stream), "cbrt weights");
-            // the padding rows U..Upad of every z block must read as zero
-            zero_pad_rows(c, St, ldz, Upad, d.U);
-            hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.ldmu, d.L, wl, ql, beta, P, d.ldmu, wz, Upad, St,
-                                   c->stream),
-                  "S gemm");
-        }
+        Forward f = run_forward(c, g, p, d);
         // (d) triple products and Gamma
-        run_triple_gather(c, p, d, prec, St, o.dev);
+        run_triple_gather(c, p, d, prec, f.St, o.dev);
         finish_out(c, o);
+    });
+}
+
+modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_problem *p,
+                                  modal_precision prec, const double *dgamma, double *dqk, double *ddelta)
+{
+    return guarded(c, [&] {
+        check_prec(c, prec);
+        Dims d = check_grid(c, g, true);
+        check_problem(c, p, d, true, true);
+        const int64_t ng = (int64_t)p->ta * p->tp;
+        need(c, dgamma != nullptr || ng == 0, MODAL_ERR_INVALID_ARG, "dgamma is NULL");
+        need(c, dqk != nullptr || ddelta != nullptr, MODAL_ERR_INVALID_ARG, "dqk and ddelta are both NULL");
+        // The step-d adjoint streams the dense moment tensor (U^3 values) once
+        // per z chunk; beyond U = 512 that traffic grows past petabytes.
+        need(c, d.U <= 512, MODAL_ERR_UNSUPPORTED,
+             "the adjoint supports np * na <= 512 in this version");
+        // inverse maps of the mode lists (ordered: the triple; symmetric: its sorted form)
+        std::vector<int> inva((size_t)d.na * d.na * d.na, -1), invp((size_t)d.np * d.np * d.np, -1);
+        auto fill = [&](const int32_t *tri, int n, int base, std::vector<int> &inv, const char *which) {
+            auto h = host_copy(c, tri, (size_t)n * 3);
+            for (int i = 0; i < n; ++i) {
+                int t0 = h[3 * i], t1 = h[3 * i + 1], t2 = h[3 * i + 2];
+                if (p->kind == MODAL_GAMMA_SYMMETRIC) {
+                    int lo = std::min(t0, std::min(t1, t2)), hi = std::max(t0, std::max(t1, t2));
+                    t1 = t0 + t1 + t2 - lo - hi;
+                    t0 = lo;
+                    t2 = hi;
+                }
+                int &slot = inv[((size_t)t0 * base + t1) * base + t2];
+                if (slot >= 0)
+                    fail(c, MODAL_ERR_SHAPE, std::string("the adjoint needs distinct triples in ") + which);
+                slot = i;
+            }
+        };
+        fill(p->tri_a, p->ta, d.na, inva, "tri_a");
+        fill(p->tri_p, p->tp, d.np, invp, "tri_p");
+
+        const double *dG = dev_in(c, dgamma, (size_t)ng);
+        OutBuf oq = dev_out(c, dqk, dqk ? (size_t)d.np * d.nk : 0, W_DQ);
+        OutBuf od = dev_out(c, ddelta, ddelta ? (size_t)d.L * d.nk : 0, W_DD);
+        Forward f = run_forward(c, g, p, d);
+        const int64_t ldz = (int64_t)d.nr * d.ldmu;
+        const int64_t upad = pad_to(d.U, kRowPad);
+
+        // (d) adjoint: H, then dL/dS chunk by chunk over z
+        int *dinva = (int *)ws_get(c, W_INVA, sizeof(int) * inva.size());
+        int *dinvp = (int *)ws_get(c, W_INVP, sizeof(int) * invp.size());
+        hipck(c, hipMemcpyAsync(dinva, inva.data(), sizeof(int) * inva.size(), hipMemcpyHostToDevice, c->stream),
+              "H2D");
+        hipck(c, hipMemcpyAsync(dinvp, invp.data(), sizeof(int) * invp.size(), hipMemcpyHostToDevice, c->stream),
+              "H2D");
+        const size_t U3 = (size_t)d.U * d.U * d.U;
+        double *H = (double *)ws_get(c, W_H, sizeof(double) * U3);
+        double *Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)d.U * ldz);
+        const size_t per_z = (size_t)d.U * d.U * sizeof(double);
+        int64_t zc = (int64_t)std::max<size_t>(64, ((size_t)1 << 31) / per_z) / 64 * 64;
+        zc = std::min<int64_t>(zc, (ldz + 63) / 64 * 64);
+        double *Y = (double *)ws_get(c, W_Y, per_z * (size_t)zc);
+        {
+            StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
+            if (ng > 0)
+                hipck(c, launch_build_h(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, H, c->stream),
+                      "build H");
+            else
+                zero(c, H, (int64_t)U3);
+            for (int64_t z0 = 0; z0 < ldz; z0 += zc) {
+                const int n = (int)std::min<int64_t>(zc, ldz - z0);
+                hipck(c, launch_shat_chunk(d.U, n, z0, upad, d.nr, d.nmu, d.ldmu, H, f.St, f.wz, Y, Shat, c->stream),
+                      "dL/dS");
+            }
+        }
+        // (c) adjoint
+        double *bhat = (double *)ws_get(c, W_BHAT, sizeof(double) * (size_t)d.np * d.L * d.nr);
+        {
+            StageTimer tm(c, MODAL_STAGE_ADJ_S);
+            hipck(c, launch_betahat(d.na, d.np, d.nr, d.ldmu, d.L, f.wl, f.ql, f.P, Shat, bhat, c->stream),
+                  "dL/dbeta");
+        }
+        // (b) adjoint: j_l regenerated in l chunks
+        {
+            StageTimer tm(c, MODAL_STAGE_ADJ_BETA);
+            const int64_t nitems = (int64_t)d.nk * d.nr;
+            BesselState st;
+            char *sb = (char *)ws_get(c, W_BSTATE, (size_t)nitems * 40);
+            st.f0 = (double *)sb;
+            st.f1 = st.f0 + nitems;
+            st.c = st.f1 + nitems;
+            st.e = (int *)(st.c + nitems);
+            st.efin = st.e + nitems;
+            const size_t per_l = (size_t)nitems * sizeof(double);
+            int cl = (int)std::max<size_t>(1, std::min<size_t>((size_t)d.L, ((size_t)512 << 20) / per_l));
+            double *jd = (double *)ws_get(c, W_JCHUNK, per_l * cl);
+            double *ah = (double *)ws_get(c, W_AHAT, sizeof(double) * (size_t)cl * d.np * d.nk);
+            hipck(c, launch_bessel_prepare(nitems, nullptr, f.G.k, d.nk, f.G.r, g->lmax, st, c->stream),
+                  "bessel prepare");
+            bool first = true;
+            for (int lhi = g->lmax; lhi >= g->lmin; lhi -= cl) {
+                const int llo = std::max(g->lmin, lhi - cl + 1), nl = lhi - llo + 1;
+                hipck(c, launch_bessel_chunk(nitems, nullptr, f.G.k, d.nk, f.G.r, lhi, llo, st, jd, nitems,
+                                             nullptr, llo, c->stream),
+                      "bessel chunk");
+                hipck(c, launch_ahat(nl, llo, g->lmin, d.L, d.np, d.nk, d.nr, bhat, jd, ah, c->stream), "Ahat");
+                hipck(c, launch_dq_ddelta(nl, llo, g->lmin, d.np, d.nk, f.G.k, f.G.wk, f.qk, f.delta, ah,
+                                          oq.dev, od.dev, first ? 1 : 0, c->stream),
+                      "dq, ddelta");
+                first = false;
+            }
+        }
+        finish_out(c, oq);
+        finish_out(c, od);
     });
 }
 

@@ -133,6 +133,21 @@ hipError_t launch_gather_bt(int kind, int ta, int tp, const int *tri_a, const in
 hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *SA,
                              hipStream_t s);
 
+// Adjoint stages (k_adjoint.hip).
+hipError_t launch_build_h(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                          const double *G, int tp, double *H, hipStream_t s);
+// dL/dS (caller layout [u][r][ldmu], zero past nmu) for z in [z0, z0 + zc)
+hipError_t launch_shat_chunk(int U, int zc, int64_t z0, int64_t upad, int nr, int nmu, int ldmu,
+                             const double *H, const double *St, const double *wz, double *Y,
+                             double *Shat, hipStream_t s);
+hipError_t launch_betahat(int na, int np, int nr, int ldmu, int L, const double *wl, const double *ql,
+                          const double *P, const double *Shat, double *bhat, hipStream_t s);
+hipError_t launch_ahat(int nl, int l0, int lmin, int L, int np, int nk, int nr, const double *bhat,
+                       const double *J, double *Ahat, hipStream_t s);
+hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const double *k, const double *wk,
+                            const double *qk, const double *delta, const double *Ahat, double *dq,
+                            double *dd, int first, hipStream_t s);
+
 // Gather Gamma entries from T.
 hipError_t launch_gather(int kind, int ta, int tp, const int *tri_a, const int *tri_p,
                          int np, const TriplePlan &plan, const double *T, double *gamma,

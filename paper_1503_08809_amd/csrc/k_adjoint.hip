@@ -1,0 +1,225 @@
+// Adjoint of the projection: the gradient of a scalar loss L of Gamma with
+// respect to the primordial basis q_p(k) and the transfer table Delta_l(k),
+// given G = dL/dGamma.  The forward stages are differentiated in reverse
+// order (Eq. (2D) -> Eq. (legendre) -> Appendix projected modes); the j_l
+// tables are regenerated in l chunks, never stored.
+//
+// Step d.  Gamma is a sum of entries of T[u1,u2,u3] = Sum_z St_u1 St_u2 St_u3
+// (St = W^(1/3) S), so with H the symmetric tensor of dL/dT,
+//     dL/dSt_u(z) = 3 Sum_{v,w} H[u,v,w] St_v(z) St_w(z).
+// H is assembled entry by entry from G (each entry gathers the Gamma entries
+// it feeds; no atomics).  The contraction is done per z chunk as
+//     Y[(u,v), z] = Sum_w H[u,v,w] St_w(z)      (FP64 matrix-core GEMM)
+//     dL/dSt_u(z) = 3 Sum_v St_v(z) Y[(u,v), z],
+// and dL/dS = W^(1/3) dL/dSt.
+// Step c.  betahat_p(l, r) = Sum_{a, mu} [w_l qbar_a(l) P_l(mu)] Shat_ap(r, mu):
+//   one GEMM per p with the (a, mu) depth and a generated A operand.
+// Step b.  Ahat_l[p, k] = Sum_r betahat_p(l, r) j_l(k r) per l on regenerated
+//   j_l chunks; then dq_p(k) = Sum_l c_k Delta_l(k) Ahat_l[p, k] and
+//   dDelta_l(k) = c_k Sum_p q_p(k) Ahat_l[p, k], c_k = (2/pi) wk k^2, with the
+//   l chunks accumulated in a fixed order (deterministic).
+#include "gemm64.hpp"
+
+namespace mp {
+namespace {
+using gemm::run;
+
+// ---- H from G -----------------------------------------------------------------
+// number of orderings of a triple that leave it unchanged
+__device__ __forceinline__ int fixers(int a, int b, int c)
+{
+    if (a == b && b == c) return 6;
+    if (a == b || b == c || a == c) return 2;
+    return 1;
+}
+
+__device__ __forceinline__ void sort3(int &a, int &b, int &c)
+{
+    int lo = min(a, min(b, c)), hi = max(a, max(b, c));
+    b = a + b + c - lo - hi;
+    a = lo;
+    c = hi;
+}
+
+__global__ void k_build_h(int kind, int U, int np, int na, const int *__restrict__ inv_a,
+                          const int *__restrict__ inv_p, const double *__restrict__ G, int tp,
+                          double *__restrict__ H)
+{
+    const int64_t n3 = (int64_t)U * U * U;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int u3 = (int)(e % U), u2 = (int)((e / U) % U), u1 = (int)(e / ((int64_t)U * U));
+        const int al[3] = {u1 / np, u2 / np, u3 / np};
+        const int rh[3] = {u1 % np, u2 % np, u3 % np};
+        double h = 0.0;
+        if (kind == MODAL_GAMMA_ORDERED) {
+            // Gamma_ord[n, m] = T(u(a1,p1), u(a2,p2), u(a3,p3)) / (8 pi): the six
+            // orderings of (u1, u2, u3) each name at most one (n, m)
+            const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const int *pi = perm[s];
+                const int n = inv_a[(al[pi[0]] * na + al[pi[1]]) * na + al[pi[2]]];
+                const int m = inv_p[(rh[pi[0]] * np + rh[pi[1]]) * np + rh[pi[2]]];
+                if (n >= 0 && m >= 0) h += G[(size_t)n * tp + m];
+            }
+            h *= 1.0 / (6.0 * 8.0 * kPi);
+        } else {
+            // Gamma_sym sums over every pairing of a with p, so H depends only on
+            // the sorted a and sorted p triples, with their fixer counts
+            int a0 = al[0], a1 = al[1], a2 = al[2], p0 = rh[0], p1 = rh[1], p2 = rh[2];
+            sort3(a0, a1, a2);
+            sort3(p0, p1, p2);
+            const int n = inv_a[(a0 * na + a1) * na + a2];
+            const int m = inv_p[(p0 * np + p1) * np + p2];
+            if (n >= 0 && m >= 0)
+                h = G[(size_t)n * tp + m] * fixers(a0, a1, a2) * fixers(p0, p1, p2) *
+                    (1.0 / (6.0 * 48.0 * kPi));
+        }
+        H[e] = h;
+    }
+}
+
+// ---- Y = H St over a z chunk ----------------------------------------------------
+struct YOp {
+    static constexpr bool a_k_fast = true;    // H[(u,v)][w]
+    static constexpr bool b_k_fast = false;   // St z-blocked: z contiguous within 32
+    int M, N, K;                              // U*U, zc, U
+    int64_t z0, upad;
+    const double *H, *St;
+    double *Y;
+    __device__ double a(int, int m, int k) const { return H[(size_t)m * K + k]; }
+    __device__ double bv(int, int k, int n) const
+    {
+        const int64_t z = z0 + n;
+        return St[(((size_t)(z >> 5) * upad + k) << 5) + (z & 31)];
+    }
+    __device__ void store(int, int m, int n, double v) const { Y[(size_t)m * N + n] = v; }
+};
+
+// Shat[u][r][mu] = W^(1/3) * 3 Sum_v St_v(z) Y[(u,v), z] over the chunk
+__global__ void k_shat(int U, int zc, int64_t z0, int64_t upad, int nmu, int ldmu,
+                       const double *__restrict__ St, const double *__restrict__ Y,
+                       const double *__restrict__ wz, double *__restrict__ Shat, int nr)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)U * zc) return;
+    const int u = (int)(i / zc), n = (int)(i % zc);
+    const int64_t z = z0 + n;
+    const double *st = St + ((size_t)(z >> 5) * upad << 5) + (z & 31);
+    const double *y = Y + (size_t)u * U * zc + n;
+    double acc = 0.0;
+    for (int v = 0; v < U; ++v) acc += st[(size_t)v << 5] * y[(size_t)v * zc];
+    const int r = (int)(z / ldmu), mu = (int)(z % ldmu);
+    if (r < nr) Shat[((size_t)u * nr + r) * ldmu + mu] = (mu < nmu) ? 3.0 * wz[z] * acc : 0.0;
+}
+
+// ---- betahat ------------------------------------------------------------------
+struct BetaHatOp {
+    static constexpr bool a_k_fast = true;    // (a, mu) with mu contiguous
+    static constexpr bool b_k_fast = true;    // Shat[u][r][mu]
+    int M, N, K;                              // L, nr, na * ldmu
+    int np, ldmu, nl;
+    const double *wl, *ql, *P, *Shat;
+    double *bhat;
+    __device__ double a(int, int l, int kk) const
+    {
+        const int ia = kk / ldmu, mu = kk % ldmu;
+        return wl[l] * ql[(size_t)ia * nl + l] * P[(size_t)l * ldmu + mu];
+    }
+    __device__ double bv(int p, int kk, int r) const
+    {
+        const int ia = kk / ldmu, mu = kk % ldmu;
+        return Shat[(((size_t)ia * np + p) * N + r) * ldmu + mu];
+    }
+    __device__ void store(int p, int l, int r, double v) const { bhat[((size_t)p * M + l) * N + r] = v; }
+};
+
+// ---- Ahat per l chunk -------------------------------------------------------------
+struct AhatOp {
+    static constexpr bool a_k_fast = true;    // bhat[p][l][r]
+    static constexpr bool b_k_fast = false;   // J[l][r][k]: k contiguous
+    int M, N, K;                              // np, nk, nr
+    int l0, lmin, L;
+    const double *bhat, *J;
+    double *Ahat;                             // [l - l0][p][k]
+    __device__ double a(int b, int p, int r) const
+    {
+        return bhat[((size_t)p * L + (l0 + b - lmin)) * K + r];
+    }
+    __device__ double bv(int b, int r, int k) const { return J[((size_t)b * K + r) * N + k]; }
+    __device__ void store(int b, int p, int k, double v) const { Ahat[((size_t)b * M + p) * N + k] = v; }
+};
+
+__global__ void k_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const double *__restrict__ k,
+                            const double *__restrict__ wk, const double *__restrict__ qk,
+                            const double *__restrict__ delta, const double *__restrict__ Ahat,
+                            double *__restrict__ dq, double *__restrict__ dd, int first)
+{
+    // one thread per k: the chunk's l values in order (deterministic)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nk) return;
+    const double ck = (2.0 / kPi) * wk[i] * k[i] * k[i];
+    for (int p = 0; p < np; ++p) {
+        double acc = 0.0;
+        for (int b = nl - 1; b >= 0; --b)
+            acc += delta[(size_t)(l0 + b - lmin) * nk + i] * Ahat[((size_t)b * np + p) * nk + i];
+        if (dq) dq[(size_t)p * nk + i] = (first ? 0.0 : dq[(size_t)p * nk + i]) + ck * acc;
+    }
+    if (dd)
+        for (int b = 0; b < nl; ++b) {
+            double acc = 0.0;
+            for (int p = 0; p < np; ++p) acc += qk[(size_t)p * nk + i] * Ahat[((size_t)b * np + p) * nk + i];
+            dd[(size_t)(l0 + b - lmin) * nk + i] = ck * acc;
+        }
+}
+
+}  // namespace
+
+hipError_t launch_build_h(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                          const double *G, int tp, double *H, hipStream_t s)
+{
+    const int64_t n3 = (int64_t)U * U * U;
+    const int64_t blocks = std::min<int64_t>((n3 + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(k_build_h, dim3((unsigned)blocks), dim3(256), 0, s, kind, U, np, na, inv_a, inv_p,
+                       G, tp, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_shat_chunk(int U, int zc, int64_t z0, int64_t upad, int nr, int nmu, int ldmu,
+                             const double *H, const double *St, const double *wz, double *Y,
+                             double *Shat, hipStream_t s)
+{
+    YOp op{U * U, zc, U, z0, upad, H, St, Y};
+    hipError_t e = run(op, 1, s);
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)U * zc;
+    hipLaunchKernelGGL(k_shat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, zc, z0, upad, nmu,
+                       ldmu, St, Y, wz, Shat, nr);
+    return hipGetLastError();
+}
+
+hipError_t launch_betahat(int na, int np, int nr, int ldmu, int L, const double *wl, const double *ql,
+                          const double *P, const double *Shat, double *bhat, hipStream_t s)
+{
+    BetaHatOp op{L, nr, na * ldmu, np, ldmu, L, wl, ql, P, Shat, bhat};
+    return run(op, np, s);
+}
+
+hipError_t launch_ahat(int nl, int l0, int lmin, int L, int np, int nk, int nr, const double *bhat,
+                       const double *J, double *Ahat, hipStream_t s)
+{
+    AhatOp op{np, nk, nr, l0, lmin, L, bhat, J, Ahat};
+    return run(op, nl, s);
+}
+
+hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const double *k, const double *wk,
+                            const double *qk, const double *delta, const double *Ahat, double *dq,
+                            double *dd, int first, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dq_ddelta, dim3((nk + 127) / 128), dim3(128), 0, s, nl, l0, lmin, np, nk, k, wk, qk,
+                       delta, Ahat, dq, dd, first);
+    return hipGetLastError();
+}
+
+}  // namespace mp

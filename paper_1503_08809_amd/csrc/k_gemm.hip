@@ -18,102 +18,11 @@
 //   contiguous slab (the triple-product kernels read a few hundred rows per
 //   step; with whole rows contiguous each step would touch a few hundred
 //   pages).
-#include "internal.hpp"
+#include "gemm64.hpp"
 
 namespace mp {
 namespace {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-constexpr int BM = 64, BN = 64, BK = 16;
-constexpr int LDA = BM + 1, LDB = BN + 1;
-
-// Op interface:
-//   static constexpr bool a_k_fast, b_k_fast;   // which index is contiguous in memory
-//   int M, N, K;
-//   double a(int b, int m, int k) const;   double bv(int b, int k, int n) const;
-//   void store(int b, int m, int n, double v) const;
-template <class Op>
-__global__ __launch_bounds__(256) void k_gemm64(Op op)
-{
-    __shared__ double As[BK][LDA];
-    __shared__ double Bs[BK][LDB];
-    const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int b = blockIdx.z;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const int M = op.M, N = op.N, K = op.K;
-
-    double ra[4], rb[4];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int m, k;
-            if (Op::a_k_fast) { k = t % BK; m = t / BK + 16 * i; }
-            else              { m = t % BM; k = t / BM + 4 * i; }
-            const int gm = m0 + m, gk = k0 + k;
-            ra[i] = (gm < M && gk < K) ? op.a(b, gm, gk) : 0.0;
-            int n, kk;
-            if (Op::b_k_fast) { kk = t % BK; n = t / BK + 16 * i; }
-            else              { n = t % BN; kk = t / BN + 4 * i; }
-            const int gn = n0 + n, gk2 = k0 + kk;
-            rb[i] = (gn < N && gk2 < K) ? op.bv(b, gk2, gn) : 0.0;
-        }
-    };
-    auto stash = [&]() {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int m, k;
-            if (Op::a_k_fast) { k = t % BK; m = t / BK + 16 * i; }
-            else              { m = t % BM; k = t / BM + 4 * i; }
-            As[k][m] = ra[i];
-            int n, kk;
-            if (Op::b_k_fast) { kk = t % BK; n = t / BK + 16 * i; }
-            else              { n = t % BN; kk = t / BN + 4 * i; }
-            Bs[kk][n] = rb[i];
-        }
-    };
-
-    d4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-    const int ktiles = (K + BK - 1) / BK;
-    load(0);
-    for (int kt = 0; kt < ktiles; ++kt) {
-        __syncthreads();
-        stash();
-        __syncthreads();
-        if (kt + 1 < ktiles) load((kt + 1) * BK);
-#pragma unroll
-        for (int ks = 0; ks < BK / 4; ++ks) {
-            const int kr = ks * 4 + (lane >> 4);
-            double av[2], bv[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = As[kr][wm * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) bv[j] = Bs[kr][wn * 32 + j * 16 + (lane & 15)];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int m = m0 + wm * 32 + i * 16 + 4 * q + (lane >> 4);
-                const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-                if (m < M && n < N) op.store(b, m, n, acc[i][j][q]);
-            }
-}
+using gemm::run;
 
 // ---- step b ----------------------------------------------------------------
 struct BetaOp {
@@ -195,15 +104,6 @@ __global__ void k_s_import(int64_t nu, int64_t upad, int nr, int nmu, int ldmu,
     const int ir = (int)(z / ldmu), im = (int)(z % ldmu);
     St[(((z >> 5) * upad + u) << 5) + (z & 31)] =
         (im < nmu) ? S[(u * nr + ir) * nmu + im] * wz[z] : 0.0;
-}
-
-template <class Op>
-hipError_t run(const Op &op, int batches, hipStream_t s)
-{
-    if (op.M <= 0 || op.N <= 0 || batches <= 0) return hipSuccess;
-    dim3 grid((op.M + BM - 1) / BM, (op.N + BN - 1) / BN, batches);
-    hipLaunchKernelGGL(k_gemm64<Op>, grid, dim3(256), 0, s, op);
-    return hipGetLastError();
 }
 
 }  // namespace

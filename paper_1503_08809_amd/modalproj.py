@@ -9,6 +9,7 @@ or no device is usable, the calls raise.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import os
 from dataclasses import dataclass
 from typing import Optional
@@ -21,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libmodalproj.so")
 
 MODAL_FP64, MODAL_MIXED = 0, 1
 ORDERED, SYMMETRIC = 0, 1
-STAGES = ("gl", "legendre", "bessel", "beta", "S", "triple", "gather")
+STAGES = ("gl", "legendre", "bessel", "beta", "S", "triple", "gather",
+          "adj_triple", "adj_S", "adj_beta")
 _PREC = {"fp64": MODAL_FP64, "mixed": MODAL_MIXED}
 _KIND = {"ordered": ORDERED, "symmetric": SYMMETRIC}
 
@@ -80,6 +82,7 @@ def lib() -> ctypes.CDLL:
             "modal_S": [vp, G, P, ctypes.c_int, vp, vp],
             "modal_gamma_from_S": [vp, G, P, ctypes.c_int, vp, vp],
             "modal_gamma": [vp, G, P, ctypes.c_int, vp],
+            "modal_gamma_backward": [vp, G, P, ctypes.c_int, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -99,7 +102,7 @@ def exported_symbols():
             "modal_last_error", "modal_set_workspace_limit", "modal_workspace_bytes",
             "modal_enable_timing", "modal_stage_times", "modal_gauss_legendre",
             "modal_legendre_table", "modal_sph_bessel_table", "modal_beta", "modal_S",
-            "modal_gamma_from_S", "modal_gamma"]
+            "modal_gamma_from_S", "modal_gamma", "modal_gamma_backward"]
 
 
 def _ptr(x) -> Optional[int]:
@@ -290,6 +293,38 @@ class Projection:
         self.ctx.check(lib().modal_gamma(self.ctx.handle, ctypes.byref(g), ctypes.byref(p),
                                          _PREC[precision], out.data_ptr()))
         return out
+
+
+    def gamma_backward(self, dgamma: torch.Tensor, precision: str = "fp64", want_q: bool = True,
+                       want_delta: bool = True):
+        """(dL/dq [np][nk], dL/ddelta [L][nk]) for dL/dGamma = dgamma."""
+        g, p = self.structs()
+        dgamma = self.ctx.to_dev(dgamma)
+        dq = self.ctx.empty(self.np_, self.k.numel()) if want_q else None
+        dd = self.ctx.empty(self.L, self.k.numel()) if want_delta else None
+        self.ctx.check(lib().modal_gamma_backward(self.ctx.handle, ctypes.byref(g), ctypes.byref(p),
+                                                  _PREC[precision], dgamma.data_ptr(),
+                                                  _ptr(dq), _ptr(dd)))
+        return dq, dd
+
+
+class ModalProjectionFunction(torch.autograd.Function):
+    """Gamma as a differentiable function of (q_p(k), Delta_l(k)); the
+    backward runs the library's adjoint (modal_gamma_backward)."""
+
+    @staticmethod
+    def forward(ctx, qk, delta, proj, precision):
+        p2 = dataclasses.replace(proj, qk=qk.detach().contiguous(), delta=delta.detach().contiguous())
+        ctx.proj = p2
+        ctx.precision = precision
+        return p2.gamma(precision)
+
+    @staticmethod
+    def backward(ctx, dgamma):
+        dq, dd = ctx.proj.gamma_backward(dgamma.contiguous(), ctx.precision,
+                                         want_q=ctx.needs_input_grad[0],
+                                         want_delta=ctx.needs_input_grad[1])
+        return dq, dd, None, None
 
 
 def projection_from_inputs(ctx: Context, inp, **over) -> Projection:

@@ -1,0 +1,149 @@
+"""Parity of the HIP adjoint (modal_gamma_backward) with the oracle's
+adjoint, its torch.autograd wrapper, and central finite differences at the
+lmax = 1000 workload.
+
+Tolerances: against the oracle the adjoint is FP64 arithmetic of sums of up
+to ~10^8 terms: normwise 1e-10.  Finite differences (absolute step 1e-6 in
+q or Delta, FP64 forward): |g_fd - g| <= 1e-6 max|g| + 1e-5 |g|.  Mixed
+forward + adjoint against the FP64 gradient: normwise 1e-4.
+"""
+import numpy as np
+import pytest
+
+from paper_1503_08809_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_08809_amd import modalproj
+    return modalproj
+
+
+@pytest.fixture(scope="module")
+def ctx(mp):
+    c = mp.Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def normwise(a, ref):
+    return float(np.abs(a - ref).max() / np.abs(ref).max())
+
+
+@pytest.mark.parametrize("kind,n1,lmax,nr,nk", [
+    ("ordered", 3, 30, 7, 80),
+    ("symmetric", 4, 30, 7, 80),
+    ("symmetric", 5, 21, 5, 50),
+    ("ordered", 1, 16, 3, 30),
+])
+def test_backward_vs_oracle(mp, ctx, oracle, kind, n1, lmax, nr, nk):
+    cfg = synth.small_config(lmax=lmax, nk=nk, nr=nr, n1=n1, kind=kind, seed_index=71)
+    inp = synth.make_inputs(cfg)
+    dG = np.random.default_rng(9).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    pr = mp.projection_from_inputs(ctx, inp)
+    dq, dd = pr.gamma_backward(ctx.to_dev(dG))
+    rq, rd = oracle.gamma_full_backward(inp, dG)
+    assert normwise(_np(dq), rq) <= 1e-10
+    assert normwise(_np(dd), rd) <= 1e-10
+
+
+def test_backward_config1_vs_oracle(mp, ctx, oracle):
+    inp = synth.make_inputs(synth.CONFIGS[1])
+    dG = np.random.default_rng(10).standard_normal((512, 512))
+    pr = mp.projection_from_inputs(ctx, inp)
+    dq, dd = pr.gamma_backward(ctx.to_dev(dG))
+    rq, rd = oracle.gamma_full_backward(inp, dG)
+    assert normwise(_np(dq), rq) <= 1e-10
+    assert normwise(_np(dd), rd) <= 1e-10
+
+
+def test_backward_host_outputs_and_null(mp, ctx):
+    import ctypes
+    inp = synth.make_inputs(synth.small_config(lmax=20, nk=40, nr=4, n1=3, kind="symmetric"))
+    pr = mp.projection_from_inputs(ctx, inp)
+    dG = np.random.default_rng(1).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    dq_dev, dd_dev = pr.gamma_backward(ctx.to_dev(dG))
+    g, p = pr.structs()
+    dq = np.zeros(inp.qk.shape)
+    ctx.check(mp.lib().modal_gamma_backward(ctx.handle, ctypes.byref(g), ctypes.byref(p), 0,
+                                            dG.ctypes.data, dq.ctypes.data, None))
+    np.testing.assert_array_equal(dq, _np(dq_dev))
+    with pytest.raises(mp.ModalError):
+        ctx.check(mp.lib().modal_gamma_backward(ctx.handle, ctypes.byref(g), ctypes.byref(p), 0,
+                                                dG.ctypes.data, None, None))
+
+
+def test_backward_rejects_repeated_triples(mp, ctx):
+    inp = synth.make_inputs(synth.small_config(lmax=20, nk=40, nr=4, n1=3, kind="symmetric"))
+    tri = inp.tri_a.copy()
+    tri[1] = tri[0][::-1]                       # same sorted triple twice
+    pr = mp.projection_from_inputs(ctx, inp, tri_a=tri)
+    dG = np.ones((tri.shape[0], inp.tri_p.shape[0]))
+    with pytest.raises(mp.ModalError) as e:
+        pr.gamma_backward(ctx.to_dev(dG))
+    assert e.value.status == 2
+
+
+def test_autograd_function(mp, ctx):
+    import torch
+    inp = synth.make_inputs(synth.small_config(lmax=24, nk=50, nr=5, n1=3, kind="symmetric"))
+    pr = mp.projection_from_inputs(ctx, inp)
+    W = ctx.to_dev(np.random.default_rng(2).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0])))
+    qk = pr.qk.clone().requires_grad_(True)
+    de = pr.delta.clone().requires_grad_(True)
+    G = mp.ModalProjectionFunction.apply(qk, de, pr, "fp64")
+    L = ((G * W) ** 2).sum()
+    L.backward()
+    dq, dd = pr.gamma_backward(2 * G.detach() * W * W)
+    np.testing.assert_allclose(_np(qk.grad), _np(dq), rtol=0, atol=0)
+    np.testing.assert_allclose(_np(de.grad), _np(dd), rtol=0, atol=0)
+
+
+def test_config4_finite_differences_and_mixed(mp, ctx):
+    """lmax = 1000, 1540 x 1540 symmetric Gamma, L = Sum (Gamma * W)^2 with W
+    a seeded N(0,1) matrix: 32 seeded entries of each gradient against
+    central differences with step 1e-6, and the mixed path's gradient
+    against the FP64 one."""
+    import torch
+    cfg = synth.CONFIGS[4]
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))
+
+    def loss(prj, prec="fp64"):
+        G = prj.gamma(prec)
+        return float(((G * W) ** 2).sum()), G
+
+    L0, G = loss(pr)
+    dq, dd = pr.gamma_backward(2 * G * W * W)
+    dq, dd = _np(dq), _np(dd)
+    h = 1e-6
+    for name, grad, off in (("qk", dq, 0), ("delta", dd, 1)):
+        base = getattr(pr, name)
+        picks = synth.pick_entries(cfg, grad.shape, 32, seed_offset=off)
+        for flat in picks:
+            idx = np.unravel_index(int(flat), grad.shape)
+            vals = []
+            for sgn in (1.0, -1.0):
+                t = base.clone()
+                t[idx] += sgn * h
+                prj = mp.projection_from_inputs(ctx, inp, **{name: t})
+                vals.append(loss(prj)[0])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            tol = 1e-6 * np.abs(grad).max() + 1e-5 * abs(grad[idx])
+            assert abs(fd - grad[idx]) <= tol, (name, idx, fd, grad[idx])
+    # mixed forward + adjoint against the FP64 gradient
+    Lm, Gm = loss(pr, "mixed")
+    mq, md = pr.gamma_backward(2 * Gm * W * W, "mixed")
+    eq, ed = normwise(_np(mq), dq), normwise(_np(md), dd)
+    print(f"mixed gradient normwise error: dq {eq:.3e}, ddelta {ed:.3e}")
+    assert eq <= 1e-4 and ed <= 1e-4
