@@ -440,8 +440,8 @@ Forward run_forward(modal_ctx c, const modal_grid *g, const modal_problem *p, co
               "cbrt weights");
         // the padding rows U..Upad of every z block must read as zero
         zero_pad_rows(c, f.St, ldz, Upad, d.U);
-        hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.ldmu, d.L, f.wl, f.ql, f.beta, f.P, d.ldmu, f.wz, Upad,
-                               f.St, c->stream),
+        hipck(c, launch_s_parity(d.na, d.np, d.nr, d.nmu, d.ldmu, d.L, g->lmin, f.wl, f.ql, f.beta, f.P, d.ldmu,
+                                 f.wz, Upad, f.St, c->stream),
               "S gemm");
     }
     return f;
@@ -744,8 +744,8 @@ modal_status modal_S(modal_ctx c, const modal_grid *g, const modal_problem *p, m
         OutBuf o = dev_out(c, S, (size_t)d.U * d.nr * d.nmu, W_ST);
         StageTimer tm(c, MODAL_STAGE_S);
         hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, cl, wl, c->stream), "weights");
-        hipck(c, launch_s_gemm(d.na, d.np, d.nr, d.nmu, d.nmu, d.L, wl, ql, dbeta, P, d.nmu, nullptr, 0,
-                               o.dev, c->stream),
+        hipck(c, launch_s_parity(d.na, d.np, d.nr, d.nmu, d.nmu, d.L, g->lmin, wl, ql, dbeta, P, d.nmu, nullptr, 0,
+                                 o.dev, c->stream),
               "S gemm");
         finish_out(c, o);
     });

@@ -43,13 +43,16 @@ __global__ __launch_bounds__(256) void k_gemm64(Op op)
             int m, k;
             if (Op::a_k_fast) { k = t % BK; m = t / BK + 16 * i; }
             else              { m = t % BM; k = t / BM + 4 * i; }
+            // clamped (always in-range) loads, zeroed by a 0/1 factor: a
+            // guarded load, or a select with a loaded operand, is compiled to
+            // a branch with its own wait for memory
             const int gm = m0 + m, gk = k0 + k;
-            ra[i] = (gm < M && gk < K) ? op.a(b, gm, gk) : 0.0;
+            ra[i] = op.a(b, min(gm, M - 1), min(gk, K - 1)) * ((gm < M && gk < K) ? 1.0 : 0.0);
             int n, kk;
             if (Op::b_k_fast) { kk = t % BK; n = t / BK + 16 * i; }
             else              { n = t % BN; kk = t / BN + 4 * i; }
             const int gn = n0 + n, gk2 = k0 + kk;
-            rb[i] = (gn < N && gk2 < K) ? op.bv(b, gk2, gn) : 0.0;
+            rb[i] = op.bv(b, min(gk2, K - 1), min(gn, N - 1)) * ((gn < N && gk2 < K) ? 1.0 : 0.0);
         }
     };
     auto stash = [&]() {
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(256) void k_gemm64(Op op)
         for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
     const int ktiles = (K + BK - 1) / BK;
-    load(0);
+    if (ktiles > 0) load(0);
     for (int kt = 0; kt < ktiles; ++kt) {
         __syncthreads();
         stash();

@@ -62,6 +62,12 @@ hipError_t launch_s_gemm(int na, int np, int nr, int nmu, int ldmu, int L,
                          const double *wl, const double *ql, const double *beta,
                          const double *P, int ldP, const double *wz, int64_t upad, double *S,
                          hipStream_t s);
+// The same product using the mu parity of P_l at nodes symmetric about 0
+// (half the work); ldP is the row length of P (nodes ascending).  Same output
+// conventions as launch_s_gemm.
+hipError_t launch_s_parity(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, const double *wl,
+                          const double *ql, const double *beta, const double *P, int ldP, const double *wz,
+                          int64_t upad, double *S, hipStream_t s);
 hipError_t launch_weights_l(int L, int lmin, double v_power, const double *cl, double *wl,
                             hipStream_t s);
 hipError_t launch_cbrt_weights(int nr, int nmu, int ldmu, const double *r, const double *wr,

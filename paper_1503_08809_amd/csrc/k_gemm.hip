@@ -23,6 +23,7 @@
 namespace mp {
 namespace {
 using gemm::run;
+using gemm::d4;
 
 // ---- step b ----------------------------------------------------------------
 struct BetaOp {
@@ -71,6 +72,152 @@ struct SOp {
         S[((size_t)u * M + m) * N + n] = (n < nmu) ? v : 0.0;
     }
 };
+
+// ---- step c with mu parity ---------------------------------------------------
+// At nodes symmetric about 0, P_l(-mu) = (-1)^l P_l(mu), so with
+// E = Sum_{l even} A P_l(mu) and O = Sum_{l odd} A P_l(mu) over mu >= 0 only,
+// S(+mu) = E + O and S(-mu) = E - O: half the work of the plain product.
+// Rows m = u * nr + r (all (a, p) pairs and radial points in one index),
+// columns j over the nh = ceil(nmu / 2) nodes mu >= 0, depth l.  Each 16-l
+// tile is stored in LDS with its even-l entries first, so that two 4-deep
+// matrix-core steps feed E and two feed O.  Workgroup tile 128 x 64, each
+// wave 32 rows x 64 columns with E and O accumulators.
+constexpr int SP_BM = 128, SP_BN = 64, SP_BK = 16;
+
+template <bool ZB>   // ZB: z-blocked output scaled by wz, else plain [u][r][ldmu]
+__global__ __launch_bounds__(256, 2) void k_s_parity(int na, int np, int nr, int nmu, int ldmu, int L, int lmin,
+                                                  const double *__restrict__ wl, const double *__restrict__ ql,
+                                                  const double *__restrict__ beta, const double *__restrict__ P,
+                                                  int ldP, const double *__restrict__ wz, int64_t upad,
+                                                  double *__restrict__ S)
+{
+    __shared__ double As[SP_BK][SP_BM + 1];
+    __shared__ double Bs[SP_BK][SP_BN + 1];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int M = na * np * nr;
+    const int nh = (nmu + 1) / 2, ioff = nmu - nh;
+    const int m0 = blockIdx.x * SP_BM, j0 = blockIdx.y * SP_BN;
+
+    // staging map: A 128 x 16 (8 per thread, rows fastest), B 16 x 64 (4 per
+    // thread); a thread's A row is fixed for the whole l loop
+    double ra[8], rb[4];
+    auto slot = [&](int kk) { return ((lmin + kk) & 1) * 8 + (kk >> 1); };
+    const int mrow = m0 + (t & 127);
+    const bool rowok = mrow < M;
+    const double *grow = nullptr, *brow = nullptr;
+    {
+        const int m = rowok ? mrow : 0;
+        const int u = m / nr, r = m % nr, ia = u / np, ip = u % np;
+        grow = ql + (size_t)ia * L;                 // wl is folded in below
+        brow = beta + (size_t)ip * L * nr + r;
+    }
+    auto load = [&](int k0) {
+        // clamped loads times a 0/1 factor (a select with a loaded operand is
+        // compiled to a branch with its own wait for memory)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int l = k0 + (t >> 7) + 2 * i, lc = min(l, L - 1);
+            ra[i] = wl[lc] * grow[lc] * brow[(size_t)lc * nr] * ((rowok && l < L) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = j0 + (t & 63), kk = (t >> 6) + 4 * i, l = k0 + kk;
+            rb[i] = P[(size_t)min(l, L - 1) * ldP + ioff + min(j, nh - 1)] * ((j < nh && l < L) ? 1.0 : 0.0);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int kk = (t >> 7) + 2 * i;
+            As[slot(kk)][t & 127] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = (t >> 6) + 4 * i;
+            Bs[slot(kk)][t & 63] = rb[i];
+        }
+    };
+
+    d4 aE[2][4], aO[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            aE[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+            aO[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+    const int ktiles = (L + SP_BK - 1) / SP_BK;
+    load(0);
+    for (int kt = 0; kt < ktiles; ++kt) {
+        __syncthreads();
+        stash();
+        __syncthreads();
+        if (kt + 1 < ktiles) load((kt + 1) * SP_BK);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double av[2], bv[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = As[kr][wave * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[kr][j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (ks < 2) aE[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], aE[i][j], 0, 0, 0);
+                    else        aO[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], aO[i][j], 0, 0, 0);
+                }
+        }
+    }
+    // epilogue: S(+mu) = E + O at node ioff + j, S(-mu) = E - O at node nh - 1 - j.
+    // The quadrature factors are loaded first, clamped and unconditionally, so
+    // that their loads overlap instead of each waiting inside a branch.
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int m = m0 + wave * 32 + i * 16 + 4 * q + (lane >> 4);
+            const int mc = min(m, M - 1);
+            const int u = mc / nr, r = mc % nr;
+            double fp[4], fm[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int jj = min(j0 + j * 16 + (lane & 15), nh - 1);
+                fp[j] = ZB ? wz[(int64_t)r * ldmu + ioff + jj] : 1.0;
+                fm[j] = ZB ? wz[(int64_t)r * ldmu + nh - 1 - jj] : 1.0;
+            }
+            if (m >= M) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int jj = j0 + j * 16 + (lane & 15);
+                if (jj >= nh) continue;
+                const double e = aE[i][j][q], o = aO[i][j][q];
+                const int ip = ioff + jj, im = nh - 1 - jj;
+                if (ZB) {
+                    const int64_t zp = (int64_t)r * ldmu + ip, zm = (int64_t)r * ldmu + im;
+                    S[(((size_t)(zp >> 5) * upad + u) << 5) + (zp & 31)] = (e + o) * fp[j];
+                    if (im != ip) S[(((size_t)(zm >> 5) * upad + u) << 5) + (zm & 31)] = (e - o) * fm[j];
+                } else {
+                    S[((size_t)u * nr + r) * ldmu + ip] = e + o;
+                    if (im != ip) S[((size_t)u * nr + r) * ldmu + im] = e - o;
+                }
+            }
+        }
+}
+
+// zero the mu padding (nodes nmu..ldmu) of z-blocked rows
+__global__ void k_zero_mu_pad(int U, int nr, int nmu, int ldmu, int64_t upad, double *__restrict__ S)
+{
+    const int pad = ldmu - nmu;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)U * nr * pad) return;
+    const int u = (int)(i / ((int64_t)nr * pad));
+    const int rem = (int)(i % ((int64_t)nr * pad));
+    const int r = rem / pad, mu = nmu + rem % pad;
+    const int64_t z = (int64_t)r * ldmu + mu;
+    S[(((size_t)(z >> 5) * upad + u) << 5) + (z & 31)] = 0.0;
+}
 
 __global__ void k_weights_l(int L, int lmin, double v_power, const double *__restrict__ cl,
                             double *__restrict__ wl)
@@ -123,6 +270,27 @@ hipError_t launch_s_gemm(int na, int np, int nr, int nmu, int ldmu, int L, const
     if (upad > 0 && (!wz || ldmu % 32 != 0)) return hipErrorInvalidValue;
     SOp op{nr, ldmu, L, np, nmu, ldP, wl, ql, beta, P, wz, S, upad};
     return run(op, na * np, s);
+}
+
+hipError_t launch_s_parity(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, const double *wl,
+                          const double *ql, const double *beta, const double *P, int ldP, const double *wz,
+                          int64_t upad, double *S, hipStream_t s)
+{
+    if (upad > 0 && (!wz || ldmu % 32 != 0)) return hipErrorInvalidValue;
+    const int M = na * np * nr, nh = (nmu + 1) / 2;
+    dim3 grid((M + SP_BM - 1) / SP_BM, (nh + SP_BN - 1) / SP_BN);
+    if (upad > 0)
+        hipLaunchKernelGGL(k_s_parity<true>, grid, dim3(256), 0, s, na, np, nr, nmu, ldmu, L, lmin, wl, ql, beta,
+                           P, ldP, wz, upad, S);
+    else
+        hipLaunchKernelGGL(k_s_parity<false>, grid, dim3(256), 0, s, na, np, nr, nmu, ldmu, L, lmin, wl, ql, beta,
+                           P, ldP, wz, upad, S);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || upad == 0 || ldmu == nmu) return e;
+    const int64_t n = (int64_t)na * np * nr * (ldmu - nmu);
+    hipLaunchKernelGGL(k_zero_mu_pad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, na * np, nr, nmu, ldmu,
+                       upad, S);
+    return hipGetLastError();
 }
 
 hipError_t launch_weights_l(int L, int lmin, double v_power, const double *cl, double *wl,
