@@ -804,10 +804,11 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         const int64_t ng = (int64_t)p->ta * p->tp;
         need(c, dgamma != nullptr || ng == 0, MODAL_ERR_INVALID_ARG, "dgamma is NULL");
         need(c, dqk != nullptr || ddelta != nullptr, MODAL_ERR_INVALID_ARG, "dqk and ddelta are both NULL");
-        // The step-d adjoint streams the dense moment tensor (U^3 values) once
-        // per z chunk; beyond U = 512 that traffic grows past petabytes.
-        need(c, d.U <= 512, MODAL_ERR_UNSUPPORTED,
-             "the adjoint supports np * na <= 512 in this version");
+        // The FP64 step-d adjoint streams the dense tensor of dL/dT (U^3
+        // values) once per z chunk; beyond U = 512 that traffic grows past
+        // petabytes.  The mixed adjoint streams it once per z tile.
+        need(c, prec == MODAL_MIXED || d.U <= 512, MODAL_ERR_UNSUPPORTED,
+             "the FP64 adjoint supports np * na <= 512 in this version");
         // inverse maps of the mode lists (ordered: the triple; symmetric: its sorted form)
         std::vector<int> inva((size_t)d.na * d.na * d.na, -1), invp((size_t)d.np * d.np * d.np, -1);
         auto fill = [&](const int32_t *tri, int n, int base, std::vector<int> &inv, const char *which) {
@@ -836,21 +837,49 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         const int64_t ldz = (int64_t)d.nr * d.ldmu;
         const int64_t upad = pad_to(d.U, kRowPad);
 
-        // (d) adjoint: H, then dL/dS chunk by chunk over z
+        // (d) adjoint: dL/dSt (z-blocked like St) from dL/dT
         int *dinva = (int *)ws_get(c, W_INVA, sizeof(int) * inva.size());
         int *dinvp = (int *)ws_get(c, W_INVP, sizeof(int) * invp.size());
         hipck(c, hipMemcpyAsync(dinva, inva.data(), sizeof(int) * inva.size(), hipMemcpyHostToDevice, c->stream),
               "H2D");
         hipck(c, hipMemcpyAsync(dinvp, invp.data(), sizeof(int) * invp.size(), hipMemcpyHostToDevice, c->stream),
               "H2D");
-        const size_t U3 = (size_t)d.U * d.U * d.U;
-        double *H = (double *)ws_get(c, W_H, sizeof(double) * U3);
-        double *Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)d.U * ldz);
-        const size_t per_z = (size_t)d.U * d.U * sizeof(double);
-        int64_t zc = (int64_t)std::max<size_t>(64, ((size_t)1 << 31) / per_z) / 64 * 64;
-        zc = std::min<int64_t>(zc, (ldz + 63) / 64 * 64);
-        double *Y = (double *)ws_get(c, W_Y, per_z * (size_t)zc);
-        {
+        const int64_t nzb = ldz / 32;
+        double *Shat = nullptr;
+        if (prec == MODAL_MIXED) {
+            // pair blocks (v block <= w block) of 16 rows; z tiles completed
+            // with zero rows of S
+            const int nvb = (d.U + 15) / 16, nib = (int)(upad / adj_mixed_rowblock());
+            std::vector<int2> pbl;
+            for (int vb = 0; vb < nvb; ++vb)
+                for (int wb = vb; wb < nvb; ++wb) pbl.push_back(make_int2(vb, wb));
+            const int npb = (int)pbl.size();
+            const int64_t nzbp = (nzb + adj_mixed_zblocks() - 1) / adj_mixed_zblocks() * adj_mixed_zblocks();
+            int2 *dpb = (int2 *)ws_get(c, W_Y, sizeof(int2) * pbl.size());
+            hipck(c, hipMemcpyAsync(dpb, pbl.data(), sizeof(int2) * pbl.size(), hipMemcpyHostToDevice, c->stream),
+                  "H2D");
+            uint4 *Hc = (uint4 *)ws_get(c, W_H, sizeof(uint4) * (size_t)npb * nib * 8192);
+            float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * (size_t)nzbp * upad * 32);
+            Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)nzbp * upad * 32);
+            StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
+            if (ng > 0) {
+                hipck(c, launch_build_hc_mixed(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib, Hc,
+                                               c->stream),
+                      "build Hc");
+            } else {
+                zero(c, (double *)Hc, (int64_t)npb * nib * 8192 * 2);
+            }
+            hipck(c, launch_f32_copy((int64_t)nzb * upad * 32, (int64_t)nzbp * upad * 32, f.St, s32, c->stream),
+                  "FP32 copy of S");
+            hipck(c, launch_adj_triple_mixed(dpb, npb, d.U, upad, nzbp, s32, Hc, Shat, c->stream), "dL/dS");
+        } else {
+            const size_t U3 = (size_t)d.U * d.U * d.U;
+            double *H = (double *)ws_get(c, W_H, sizeof(double) * U3);
+            Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)nzb * upad * 32);
+            const size_t per_z = (size_t)d.U * d.U * sizeof(double);
+            int64_t zc = (int64_t)std::max<size_t>(64, ((size_t)1 << 31) / per_z) / 64 * 64;
+            zc = std::min<int64_t>(zc, (ldz + 63) / 64 * 64);
+            double *Y = (double *)ws_get(c, W_Y, per_z * (size_t)zc);
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
             if (ng > 0)
                 hipck(c, launch_build_h(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, H, c->stream),
@@ -859,15 +888,15 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
                 zero(c, H, (int64_t)U3);
             for (int64_t z0 = 0; z0 < ldz; z0 += zc) {
                 const int n = (int)std::min<int64_t>(zc, ldz - z0);
-                hipck(c, launch_shat_chunk(d.U, n, z0, upad, d.nr, d.nmu, d.ldmu, H, f.St, f.wz, Y, Shat, c->stream),
-                      "dL/dS");
+                hipck(c, launch_shat_chunk(d.U, n, z0, upad, H, f.St, Y, Shat, c->stream), "dL/dS");
             }
         }
         // (c) adjoint
         double *bhat = (double *)ws_get(c, W_BHAT, sizeof(double) * (size_t)d.np * d.L * d.nr);
         {
             StageTimer tm(c, MODAL_STAGE_ADJ_S);
-            hipck(c, launch_betahat(d.na, d.np, d.nr, d.ldmu, d.L, f.wl, f.ql, f.P, Shat, bhat, c->stream),
+            hipck(c, launch_betahat(d.na, d.np, d.nr, d.ldmu, d.L, upad, f.wl, f.ql, f.P, Shat, f.wz, bhat,
+                                    c->stream),
                   "dL/dbeta");
         }
         // (b) adjoint: j_l regenerated in l chunks

@@ -142,12 +142,28 @@ hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *
 // Adjoint stages (k_adjoint.hip).
 hipError_t launch_build_h(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
                           const double *G, int tp, double *H, hipStream_t s);
-// dL/dS (caller layout [u][r][ldmu], zero past nmu) for z in [z0, z0 + zc)
-hipError_t launch_shat_chunk(int U, int zc, int64_t z0, int64_t upad, int nr, int nmu, int ldmu,
-                             const double *H, const double *St, const double *wz, double *Y,
-                             double *Shat, hipStream_t s);
-hipError_t launch_betahat(int na, int np, int nr, int ldmu, int L, const double *wl, const double *ql,
-                          const double *P, const double *Shat, double *bhat, hipStream_t s);
+// dL/dSt (z-blocked like St, upad rows per block) for z in [z0, z0 + zc) from
+// the dense H [U][U][U], through Y[(u,v)][z] = Sum_w H St_w (zc columns)
+hipError_t launch_shat_chunk(int U, int zc, int64_t z0, int64_t upad, const double *H, const double *St,
+                             double *Y, double *Shat, hipStream_t s);
+// Mixed adjoint of step d: Hc in the kernel's operand order from G, for
+// pair blocks pblocks[npb] (16-row v block <= w block) and nib row blocks
+hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                                 const double *G, int tp, const int2 *pblocks, int npb, int nib, uint4 *Hc,
+                                 hipStream_t s);
+// dL/dSt from Hc and the FP32 rows S32 (z-blocked, nzb z blocks: a multiple
+// of adj_mixed_zblocks(), zero past the data; upad a multiple of
+// adj_mixed_rowblock()); rows >= U of Shat are left unwritten.
+hipError_t launch_adj_triple_mixed(const int2 *pblocks, int npb, int U, int64_t upad, int64_t nzb,
+                                   const float *S32, const uint4 *Hc, double *Shat, hipStream_t s);
+int adj_mixed_zblocks();
+int adj_mixed_rowblock();
+// S32[i] = St[i] for i < n, 0 for n <= i < ntot
+hipError_t launch_f32_copy(int64_t n, int64_t ntot, const double *St, float *S32, hipStream_t s);
+// dL/dbeta from dL/dSt (z-blocked, times wz on read)
+hipError_t launch_betahat(int na, int np, int nr, int ldmu, int L, int64_t upad, const double *wl,
+                          const double *ql, const double *P, const double *Shat, const double *wz, double *bhat,
+                          hipStream_t s);
 hipError_t launch_ahat(int nl, int l0, int lmin, int L, int np, int nk, int nr, const double *bhat,
                        const double *J, double *Ahat, hipStream_t s);
 hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const double *k, const double *wk,

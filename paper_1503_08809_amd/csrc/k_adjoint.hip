@@ -20,6 +20,8 @@
 //   l chunks accumulated in a fixed order (deterministic).
 #include "gemm64.hpp"
 
+#include <algorithm>
+
 namespace mp {
 namespace {
 using gemm::run;
@@ -41,6 +43,39 @@ __device__ __forceinline__ void sort3(int &a, int &b, int &c)
     c = hi;
 }
 
+// H[u1,u2,u3] (symmetric) for rows u = a * np + p
+__device__ double adj_h(int kind, int np, int na, const int *__restrict__ inv_a, const int *__restrict__ inv_p,
+                        const double *__restrict__ G, int tp, int u1, int u2, int u3)
+{
+    const int al[3] = {u1 / np, u2 / np, u3 / np};
+    const int rh[3] = {u1 % np, u2 % np, u3 % np};
+    double h = 0.0;
+    if (kind == MODAL_GAMMA_ORDERED) {
+        // Gamma_ord[n, m] = T(u(a1,p1), u(a2,p2), u(a3,p3)) / (8 pi): the six
+        // orderings of (u1, u2, u3) each name at most one (n, m)
+        const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const int *pi = perm[s];
+            const int n = inv_a[(al[pi[0]] * na + al[pi[1]]) * na + al[pi[2]]];
+            const int m = inv_p[(rh[pi[0]] * np + rh[pi[1]]) * np + rh[pi[2]]];
+            if (n >= 0 && m >= 0) h += G[(size_t)n * tp + m];
+        }
+        h *= 1.0 / (6.0 * 8.0 * kPi);
+    } else {
+        // Gamma_sym sums over every pairing of a with p, so H depends only on
+        // the sorted a and sorted p triples, with their fixer counts
+        int a0 = al[0], a1 = al[1], a2 = al[2], p0 = rh[0], p1 = rh[1], p2 = rh[2];
+        sort3(a0, a1, a2);
+        sort3(p0, p1, p2);
+        const int n = inv_a[(a0 * na + a1) * na + a2];
+        const int m = inv_p[(p0 * np + p1) * np + p2];
+        if (n >= 0 && m >= 0)
+            h = G[(size_t)n * tp + m] * fixers(a0, a1, a2) * fixers(p0, p1, p2) * (1.0 / (6.0 * 48.0 * kPi));
+    }
+    return h;
+}
+
 __global__ void k_build_h(int kind, int U, int np, int na, const int *__restrict__ inv_a,
                           const int *__restrict__ inv_p, const double *__restrict__ G, int tp,
                           double *__restrict__ H)
@@ -49,34 +84,53 @@ __global__ void k_build_h(int kind, int U, int np, int na, const int *__restrict
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int u3 = (int)(e % U), u2 = (int)((e / U) % U), u1 = (int)(e / ((int64_t)U * U));
-        const int al[3] = {u1 / np, u2 / np, u3 / np};
-        const int rh[3] = {u1 % np, u2 % np, u3 % np};
-        double h = 0.0;
-        if (kind == MODAL_GAMMA_ORDERED) {
-            // Gamma_ord[n, m] = T(u(a1,p1), u(a2,p2), u(a3,p3)) / (8 pi): the six
-            // orderings of (u1, u2, u3) each name at most one (n, m)
-            const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        H[e] = adj_h(kind, np, na, inv_a, inv_p, G, tp, u1, u2, u3);
+    }
+}
+
+// Hc[u][(v,w)] = 3 c_vw H[u,v,w] (c = 2 for v < w, 1 for v = w, 0 for v > w)
+// split into BF16 hi and lo, in the A-operand order of the mixed adjoint
+// kernel: Hc[pair block][row block of 128][step][row tile][hi/lo][lane], a
+// lane holding rows 16-tile + lane % 16 and step pairs 8 (lane / 16) .. + 7.
+__device__ __forceinline__ uint32_t bf16_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__global__ void k_build_hc_mx(int kind, int U, int np, int na, const int *__restrict__ inv_a,
+                              const int *__restrict__ inv_p, const double *__restrict__ G, int tp,
+                              const int2 *__restrict__ pblocks, int npb, int nib, uint4 *__restrict__ Hc)
+{
+    const int64_t n = (int64_t)npb * nib * 8 * 8 * 64;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(e & 63), rt = (int)((e >> 6) & 7), ks = (int)((e >> 9) & 7);
+        const int64_t pbib = e >> 12;
+        const int ib = (int)(pbib % nib), pb = (int)(pbib / nib);
+        const int2 b = pblocks[pb];
+        const int u = ib * 128 + rt * 16 + (lane & 15);
+        float x[8];
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                const int *pi = perm[s];
-                const int n = inv_a[(al[pi[0]] * na + al[pi[1]]) * na + al[pi[2]]];
-                const int m = inv_p[(rh[pi[0]] * np + rh[pi[1]]) * np + rh[pi[2]]];
-                if (n >= 0 && m >= 0) h += G[(size_t)n * tp + m];
-            }
-            h *= 1.0 / (6.0 * 8.0 * kPi);
-        } else {
-            // Gamma_sym sums over every pairing of a with p, so H depends only on
-            // the sorted a and sorted p triples, with their fixer counts
-            int a0 = al[0], a1 = al[1], a2 = al[2], p0 = rh[0], p1 = rh[1], p2 = rh[2];
-            sort3(a0, a1, a2);
-            sort3(p0, p1, p2);
-            const int n = inv_a[(a0 * na + a1) * na + a2];
-            const int m = inv_p[(p0 * np + p1) * np + p2];
-            if (n >= 0 && m >= 0)
-                h = G[(size_t)n * tp + m] * fixers(a0, a1, a2) * fixers(p0, p1, p2) *
-                    (1.0 / (6.0 * 48.0 * kPi));
+        for (int q = 0; q < 8; ++q) {
+            const int pi = 32 * ks + 8 * (lane >> 4) + q;
+            const int v = b.x * 16 + (pi >> 4), w = b.y * 16 + (pi & 15);
+            double h = 0.0;
+            if (u < U && v < U && w < U && v <= w)
+                h = (v < w ? 6.0 : 3.0) * adj_h(kind, np, na, inv_a, inv_p, G, tp, u, v, w);
+            x[q] = (float)h;
         }
-        H[e] = h;
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t h0 = bf16_bits(x[2 * q]), h1 = bf16_bits(x[2 * q + 1]);
+            hi[q] = h0 | (h1 << 16);
+            lo[q] = bf16_bits(x[2 * q] - __uint_as_float(h0 << 16)) |
+                    (bf16_bits(x[2 * q + 1] - __uint_as_float(h1 << 16)) << 16);
+        }
+        uint4 *o = Hc + ((e >> 6) << 7) + lane;        // [.. row tile][hi/lo][lane]
+        o[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        o[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
     }
 }
 
@@ -97,10 +151,10 @@ struct YOp {
     __device__ void store(int, int m, int n, double v) const { Y[(size_t)m * N + n] = v; }
 };
 
-// Shat[u][r][mu] = W^(1/3) * 3 Sum_v St_v(z) Y[(u,v), z] over the chunk
-__global__ void k_shat(int U, int zc, int64_t z0, int64_t upad, int nmu, int ldmu,
-                       const double *__restrict__ St, const double *__restrict__ Y,
-                       const double *__restrict__ wz, double *__restrict__ Shat, int nr)
+// Shat_u(z) = 3 Sum_v St_v(z) Y[(u,v), z] over the chunk: dL/dSt, z-blocked
+// like St (the W^(1/3) factor is applied where it is read)
+__global__ void k_shat(int U, int zc, int64_t z0, int64_t upad, const double *__restrict__ St,
+                       const double *__restrict__ Y, double *__restrict__ Shat)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)U * zc) return;
@@ -110,27 +164,29 @@ __global__ void k_shat(int U, int zc, int64_t z0, int64_t upad, int nmu, int ldm
     const double *y = Y + (size_t)u * U * zc + n;
     double acc = 0.0;
     for (int v = 0; v < U; ++v) acc += st[(size_t)v << 5] * y[(size_t)v * zc];
-    const int r = (int)(z / ldmu), mu = (int)(z % ldmu);
-    if (r < nr) Shat[((size_t)u * nr + r) * ldmu + mu] = (mu < nmu) ? 3.0 * wz[z] * acc : 0.0;
+    Shat[(((size_t)(z >> 5) * upad + u) << 5) + (z & 31)] = 3.0 * acc;
 }
 
 // ---- betahat ------------------------------------------------------------------
 struct BetaHatOp {
     static constexpr bool a_k_fast = true;    // (a, mu) with mu contiguous
-    static constexpr bool b_k_fast = true;    // Shat[u][r][mu]
+    static constexpr bool b_k_fast = true;    // Shat z-blocked: mu contiguous within 32
     int M, N, K;                              // L, nr, na * ldmu
     int np, ldmu, nl;
-    const double *wl, *ql, *P, *Shat;
+    int64_t upad;
+    const double *wl, *ql, *P, *Shat, *wz;
     double *bhat;
     __device__ double a(int, int l, int kk) const
     {
         const int ia = kk / ldmu, mu = kk % ldmu;
         return wl[l] * ql[(size_t)ia * nl + l] * P[(size_t)l * ldmu + mu];
     }
+    // dL/dS = W^(1/3) dL/dSt
     __device__ double bv(int p, int kk, int r) const
     {
         const int ia = kk / ldmu, mu = kk % ldmu;
-        return Shat[(((size_t)ia * np + p) * N + r) * ldmu + mu];
+        const int64_t z = (int64_t)r * ldmu + mu;
+        return wz[z] * Shat[(((size_t)(z >> 5) * upad + ia * np + p) << 5) + (z & 31)];
     }
     __device__ void store(int p, int l, int r, double v) const { bhat[((size_t)p * M + l) * N + r] = v; }
 };
@@ -186,23 +242,35 @@ hipError_t launch_build_h(int kind, int U, int np, int na, const int *inv_a, con
     return hipGetLastError();
 }
 
-hipError_t launch_shat_chunk(int U, int zc, int64_t z0, int64_t upad, int nr, int nmu, int ldmu,
-                             const double *H, const double *St, const double *wz, double *Y,
-                             double *Shat, hipStream_t s)
+hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                                 const double *G, int tp, const int2 *pblocks, int npb, int nib, uint4 *Hc,
+                                 hipStream_t s)
+{
+    const int64_t n = (int64_t)npb * nib * 8 * 8 * 64;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_hc_mx, dim3((unsigned)blocks), dim3(256), 0, s, kind, U, np, na, inv_a, inv_p,
+                       G, tp, pblocks, npb, nib, Hc);
+    return hipGetLastError();
+}
+
+hipError_t launch_shat_chunk(int U, int zc, int64_t z0, int64_t upad, const double *H, const double *St,
+                             double *Y, double *Shat, hipStream_t s)
 {
     YOp op{U * U, zc, U, z0, upad, H, St, Y};
     hipError_t e = run(op, 1, s);
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)U * zc;
-    hipLaunchKernelGGL(k_shat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, zc, z0, upad, nmu,
-                       ldmu, St, Y, wz, Shat, nr);
+    hipLaunchKernelGGL(k_shat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, zc, z0, upad, St, Y,
+                       Shat);
     return hipGetLastError();
 }
 
-hipError_t launch_betahat(int na, int np, int nr, int ldmu, int L, const double *wl, const double *ql,
-                          const double *P, const double *Shat, double *bhat, hipStream_t s)
+hipError_t launch_betahat(int na, int np, int nr, int ldmu, int L, int64_t upad, const double *wl,
+                          const double *ql, const double *P, const double *Shat, const double *wz, double *bhat,
+                          hipStream_t s)
 {
-    BetaHatOp op{L, nr, na * ldmu, np, ldmu, L, wl, ql, P, Shat, bhat};
+    BetaHatOp op{L, nr, na * ldmu, np, ldmu, L, upad, wl, ql, P, Shat, wz, bhat};
     return run(op, np, s);
 }
 

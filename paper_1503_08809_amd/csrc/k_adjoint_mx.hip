@@ -1,0 +1,313 @@
+// Step d adjoint, mixed precision: dL/dSt from the symmetric tensor H of
+// dL/dT (T the third moments of the W^(1/3)-scaled S rows, see
+// k_triple_mx.hip), as
+//     Shat_u(z) = 3 Sum_{v,w} H[u,v,w] St_v(z) St_w(z)
+//               = Sum_{v <= w} Hc[u][(v,w)] St_v(z) St_w(z),
+//     Hc[u][(v,w)] = 3 c_vw H[u,v,w],  c_vw = 2 (v < w), 1 (v = w).
+// This is a product with a generated right operand: rows u, columns z, depth
+// the pairs (v, w).  Pairs come in blocks of 16 x 16 (v block <= w block;
+// inside a diagonal block Hc is zero for v > w), 32 pairs per matrix-core
+// step.  It costs three times the forward product (each unique triple feeds
+// three outputs) and, unlike the forward, reduces over pairs, not z.
+//
+// Work decomposition: a workgroup owns the output tile of 128 rows u times
+// 256 values z and runs over every pair block.  Hc is stored pre-split
+// (BF16 hi, lo) in the matrix-core A-operand order, so one 128 x 256-pair
+// block is a contiguous 128 KB read; tasks are ordered (row block, z tile)
+// and dealt to the XCDs in contiguous runs, so the workgroups of one XCD
+// stream the same Hc blocks through their shared L2.  The operand
+// St_v(z) St_w(z) is formed in FP32 from the 32 source rows of the pair
+// block (staged in LDS once per block), split into BF16 hi and lo, and
+// shared through LDS by the eight waves (double-buffered per step).
+//
+// Arithmetic: A_lo B_hi + A_hi B_lo + A_hi B_hi per term on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation over kFlush pair blocks,
+// then added to the FP64 output (each workgroup owns its tile: a plain
+// read-modify-write, deterministic).
+#include "internal.hpp"
+
+#include <algorithm>
+
+namespace mp {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int AI = 128;            // output rows per workgroup
+constexpr int PB = 16;             // pair block: 16 v x 16 w
+constexpr int KS = PB * PB / 32;   // 32-pair steps per pair block
+constexpr int ZT = 256;            // z values per workgroup
+constexpr int NCT = ZT / 16;       // 16-wide column tiles
+constexpr int ZBW = ZT / 32;       // z blocks of 32 per workgroup
+constexpr int kFlush = 32;         // pair blocks per FP32 partial sum
+constexpr int SJ_LD = ZT + 4;      // padded LDS rows (floats)
+constexpr int SK_LD = PB + 4;
+
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);       // lgkmcnt(0) only: global loads stay in flight
+    __builtin_amdgcn_s_barrier();
+}
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ bf8 as_bf8(uint4 v)
+{
+    bf8 r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+
+struct AdjArgs {
+    const int2 *pblocks;    // (v block, w block), v block <= w block
+    int npb;
+    int nib;                // row blocks of AI
+    int nzt;                // z tiles of ZT
+    int U;                  // rows holding data (rows >= U are zero)
+    int64_t upad;           // rows per z block of the z-blocked layouts
+};
+
+__global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restrict__ S32,
+                                                const uint4 *__restrict__ Hc, double *__restrict__ Shat)
+{
+    __shared__ float SrcJ[2][PB][SJ_LD];      // [pair-block parity][v local][z]
+    __shared__ float SrcK[2][ZT][SK_LD];      // [pair-block parity][z][w local]
+    __shared__ uint4 Bb[2][NCT][2][64];       // [step parity][column tile][hi/lo][lane]
+
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int rg = wave & 3, ch = wave >> 2;   // 32-row group, 8-tile column half
+    // tasks (row block, z tile), row block outer, dealt to the 8 XCDs in
+    // contiguous runs
+    const int ntasks = A.nib * A.nzt;
+    const int task = [&] {
+        const int x = blockIdx.x & 7, idx = blockIdx.x >> 3;
+        const int base = ntasks >> 3, rem = ntasks & 7;
+        return x * base + (x < rem ? x : rem) + idx;
+    }();
+    const int ib = task / A.nzt, zt = task % A.nzt;
+    const int64_t zb0 = (int64_t)zt * ZBW;
+    const int u0 = ib * AI + rg * 32;
+    const bool active = u0 < A.U;              // wave-uniform: some row holds data
+
+    f4 acc[2][8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // ---- staging of a pair block's 32 source rows over the z tile: 2048
+    // float4, four per thread.  v rows (i = 0, 1): a wave covers one row's
+    // 256 z (contiguous LDS writes); w rows (i = 2, 3): consecutive lanes take
+    // consecutive rows, so the transposed LDS writes spread over the banks.
+    f4 sreg[4];
+    auto sload = [&](int pb) {
+        const int2 b = A.pblocks[pb];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = t + 512 * (i & 1);
+            int grow, z4;
+            if (i < 2) { grow = b.x * PB + (f >> 6); z4 = f & 63; }
+            else       { grow = b.y * PB + (f & 15); z4 = f >> 4; }
+            sreg[i] = *reinterpret_cast<const f4 *>(S32 + (((zb0 + (z4 >> 3)) * A.upad + grow) << 5) +
+                                                    4 * (z4 & 7));
+        }
+    };
+    auto sstore = [&](int sb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = t + 512 * (i & 1);
+            if (i < 2) {
+                *reinterpret_cast<f4 *>(&SrcJ[sb][f >> 6][4 * (f & 63)]) = sreg[i];
+            } else {
+                const int zl = 4 * (f >> 4), row = f & 15;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) SrcK[sb][zl + e][row] = sreg[i][e];
+            }
+        }
+    };
+    // ---- operand of step ks of the pair block staged in SrcJ/K[sb]: column
+    // tiles 2 wave, 2 wave + 1.  Lane: z = tile * 16 + lane % 16, v local =
+    // 2 ks + lane / 32, w local = 8 ((lane / 16) % 2) + e (matrix-core depth
+    // index 8 (lane / 16) + e of the step)
+    auto bgen = [&](int sb, int ks, int bb) {
+        const int vl = 2 * ks + (lane >> 5), wh = ((lane >> 4) & 1) * 8;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int ct = 2 * wave + q, zl = ct * 16 + (lane & 15);
+            const float sv = SrcJ[sb][vl][zl];
+            const f4 w0 = *reinterpret_cast<const f4 *>(&SrcK[sb][zl][wh]);
+            const f4 w1 = *reinterpret_cast<const f4 *>(&SrcK[sb][zl][wh + 4]);
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = sv * w0[e];
+                v[4 + e] = sv * w1[e];
+            }
+            uint32_t h[4], l[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t h0 = bf16_rne_bits(v[2 * e]), h1 = bf16_rne_bits(v[2 * e + 1]);
+                const float r0 = v[2 * e] - __uint_as_float(h0 << 16);
+                const float r1 = v[2 * e + 1] - __uint_as_float(h1 << 16);
+                h[e] = h0 | (h1 << 16);
+                l[e] = bf16_rne_bits(r0) | (bf16_rne_bits(r1) << 16);
+            }
+            Bb[bb][ct][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
+            Bb[bb][ct][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
+        }
+    };
+    // ---- A fragments (Hc) of step (pb, ks) for this wave's two row tiles:
+    // Hc[pb][ib][ks][row tile][hi/lo][lane]
+    uint4 ah[2], al[2];
+    auto aload = [&](int pb, int ks) {
+        const uint4 *p = Hc + ((((size_t)pb * A.nib + ib) * KS + ks) * 8 + 2 * rg) * 128 + lane;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            ah[i] = p[i * 128];
+            al[i] = p[i * 128 + 64];
+        }
+    };
+
+    // ---- output: this wave's tiles (row tile i, column tile 8 ch + j) at
+    // Shat[zb][u][32], u = u0 + 16 i + 4 (lane / 16) + q, z = 16 (8 ch + j) + lane % 16
+    const int zl0 = ch * 128 + (lane & 15);
+    auto flush = [&](bool first) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int ub = u0 + 16 * i + 4 * (lane >> 4);
+            double old[8][4];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int zl = zl0 + 16 * j;
+                const double *p = Shat + ((((zb0 + (zl >> 5)) * A.upad + ub) << 5) + (zl & 31));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) old[j][q] = first ? 0.0 : p[q * 32];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int zl = zl0 + 16 * j;
+                double *p = Shat + ((((zb0 + (zl >> 5)) * A.upad + ub) << 5) + (zl & 31));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) p[q * 32] = old[j][q] + (double)acc[i][j][q];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    };
+
+    const int npb = A.npb;
+    // prologue: sources of pair block 0, operand of step (0, 0), A of (0, 0),
+    // and the loads of pair block 1's sources
+    sload(0);
+    sstore(0);
+    lds_barrier();
+    bgen(0, 0, 0);
+    aload(0, 0);
+    sload(npb > 1 ? 1 : 0);
+    lds_barrier();
+
+    int since_flush = 0;
+    bool first = true;
+    for (int pb = 0; pb < npb; ++pb) {
+        const int sb = pb & 1;
+#pragma unroll 1
+        for (int ks = 0; ks < KS; ++ks) {
+            const int bb = ks & 1;             // KS is even: step parity = ks parity
+            // the step after this one: next ks, or step 0 of the next pair block
+            const bool last_step = ks == KS - 1;
+            const int nsb = last_step ? sb ^ 1 : sb, nks = last_step ? 0 : ks + 1;
+            const bool has_next = !(last_step && pb + 1 == npb);
+            if (active) {
+                uint4 bh = Bb[bb][ch * 8][0][lane], bl = Bb[bb][ch * 8][1][lane];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    uint4 nbh = bh, nbl = bl;
+                    if (j + 1 < 8) {
+                        nbh = Bb[bb][ch * 8 + j + 1][0][lane];
+                        nbl = Bb[bb][ch * 8 + j + 1][1][lane];
+                    }
+                    const bf8 h8 = as_bf8(bh), l8 = as_bf8(bl);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), h8, acc[i][j], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), l8, acc[i][j], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), h8, acc[i][j], 0, 0, 0);
+                    if (j == 3 && has_next) bgen(nsb, nks, bb ^ 1);     // operand of the next step
+                    __builtin_amdgcn_sched_barrier(0);
+                    bh = nbh;
+                    bl = nbl;
+                }
+            } else if (has_next) {
+                bgen(nsb, nks, bb ^ 1);
+            }
+            // sources of pair block pb + 1 into the other buffer (free since
+            // the operand of this block's step 0 was generated), and the loads
+            // of pair block pb + 2's sources
+            if (ks == KS / 2) {
+                sstore(sb ^ 1);
+                sload(pb + 2 < npb ? pb + 2 : npb - 1);
+            }
+            if (last_step && (++since_flush == kFlush || pb + 1 == npb)) {
+                if (active) flush(first);
+                since_flush = 0;
+                first = false;
+            }
+            if (has_next) aload(last_step ? pb + 1 : pb, nks);
+            lds_barrier();
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adj_triple_mixed(const int2 *pblocks, int npb, int U, int64_t upad, int64_t nzb,
+                                   const float *S32, const uint4 *Hc, double *Shat, hipStream_t s)
+{
+    if (upad % AI != 0 || upad < U || nzb % ZBW != 0 || npb <= 0) return hipErrorInvalidValue;
+    AdjArgs a;
+    a.pblocks = pblocks;
+    a.npb = npb;
+    a.nib = (int)(upad / AI);
+    a.nzt = (int)(nzb / ZBW);
+    a.U = U;
+    a.upad = upad;
+    const int64_t ntasks = (int64_t)a.nib * a.nzt;
+    if (ntasks == 0) return hipSuccess;
+    if (ntasks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_bt, dim3((unsigned)ntasks), dim3(512), 0, s, a, S32, Hc, Shat);
+    return hipGetLastError();
+}
+
+// FP32 copy of the first n values of St, zeros up to ntot (the z tail that
+// completes the last z tile)
+__global__ void k_f32_copy(int64_t n, int64_t ntot, const double *__restrict__ St, float *__restrict__ S32)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot;
+         i += (int64_t)gridDim.x * blockDim.x)
+        S32[i] = i < n ? (float)St[i] : 0.f;
+}
+
+hipError_t launch_f32_copy(int64_t n, int64_t ntot, const double *St, float *S32, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((ntot + 255) / 256, 1 << 20);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_f32_copy, dim3((unsigned)blocks), dim3(256), 0, s, n, ntot, St, S32);
+    return hipGetLastError();
+}
+
+int adj_mixed_zblocks() { return ZBW; }
+int adj_mixed_rowblock() { return AI; }
+
+}  // namespace mp

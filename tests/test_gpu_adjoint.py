@@ -56,6 +56,39 @@ def test_backward_vs_oracle(mp, ctx, oracle, kind, n1, lmax, nr, nk):
     assert normwise(_np(dd), rd) <= 1e-10
 
 
+@pytest.mark.parametrize("kind,n1,lmax,nr,nk", [
+    ("ordered", 3, 30, 7, 80),
+    ("symmetric", 5, 21, 5, 50),
+    ("symmetric", 6, 26, 4, 40),      # U = 36: three 16-row blocks, ragged
+    ("ordered", 1, 16, 3, 30),
+])
+def test_backward_mixed_vs_oracle(mp, ctx, oracle, kind, n1, lmax, nr, nk):
+    """Mixed adjoint of step d (split-BF16 products, FP32 partial sums,
+    FP64 output) against the FP64 oracle: normwise 1e-4."""
+    cfg = synth.small_config(lmax=lmax, nk=nk, nr=nr, n1=n1, kind=kind, seed_index=72)
+    inp = synth.make_inputs(cfg)
+    dG = np.random.default_rng(12).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    pr = mp.projection_from_inputs(ctx, inp)
+    dq, dd = pr.gamma_backward(ctx.to_dev(dG), "mixed")
+    rq, rd = oracle.gamma_full_backward(inp, dG)
+    eq, ed = normwise(_np(dq), rq), normwise(_np(dd), rd)
+    print(f"mixed adjoint {kind} n1={n1}: dq {eq:.2e}, ddelta {ed:.2e}")
+    assert eq <= 1e-4 and ed <= 1e-4
+
+
+def test_backward_mixed_config2_vs_fp64(mp, ctx):
+    """lmax = 500, U = 256 ordered: the mixed adjoint against the FP64 one."""
+    inp = synth.make_inputs(synth.CONFIGS[2])
+    dG = np.random.default_rng(13).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    pr = mp.projection_from_inputs(ctx, inp)
+    G = ctx.to_dev(dG)
+    fq, fd = pr.gamma_backward(G, "fp64")
+    mq, md = pr.gamma_backward(G, "mixed")
+    eq, ed = normwise(_np(mq), _np(fq)), normwise(_np(md), _np(fd))
+    print(f"mixed vs FP64 adjoint at lmax=500: dq {eq:.2e}, ddelta {ed:.2e}")
+    assert eq <= 1e-4 and ed <= 1e-4
+
+
 def test_backward_config1_vs_oracle(mp, ctx, oracle):
     inp = synth.make_inputs(synth.CONFIGS[1])
     dG = np.random.default_rng(10).standard_normal((512, 512))
