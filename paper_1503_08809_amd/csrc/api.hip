@@ -20,7 +20,7 @@ thread_local std::string g_last_error;   // for calls without a usable context
 enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
     W_S32, W_SH, W_SL, W_GAMMA,
-    W_INVA, W_INVP, W_H, W_SHAT, W_Y, W_BHAT, W_AHAT, W_DQ, W_DD,
+    W_INVA, W_INVP, W_H, W_SHAT, W_PBL, W_BHAT, W_AHAT, W_DQ, W_DD,
     W_IN0, NSLOTS = W_IN0 + 16
 };
 
@@ -431,8 +431,12 @@ Forward run_forward(modal_ctx c, const modal_grid *g, const modal_problem *p, co
     f.beta = (double *)ws_get(c, W_BETA, sizeof(double) * (size_t)d.np * d.L * d.nr);
     run_beta(c, g, d, f.G, f.delta, f.qk, f.beta);
     // (c) the l contraction, scaled rows
+    // St holds whole groups of kZBlockPad z blocks; the blocks past ldz are
+    // zero (the adjoint kernels work on whole z tiles)
     const int Upad = pad_to(d.U, kRowPad);
-    f.St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * ldz);
+    const int64_t nzb = ldz / 32, nzbp = (nzb + kZBlockPad - 1) / kZBlockPad * kZBlockPad;
+    f.St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * nzbp * 32);
+    zero(c, f.St + (size_t)nzb * Upad * 32, (nzbp - nzb) * Upad * 32);
     {
         StageTimer tm(c, MODAL_STAGE_S);
         hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, f.cl, f.wl, c->stream), "weights");
@@ -645,7 +649,7 @@ modal_status modal_workspace_bytes(modal_ctx c, const modal_grid *g, const modal
         size_t b = 0;
         b += 2 * d.nmu * 8 + (size_t)d.L * d.ldmu * 8 + d.L * 8 + z * 8;
         b += nitems * 40 + cl * nitems * 8 + (size_t)d.np * d.L * d.nr * 8;
-        b += Upad * z * 8 + tsize * 8;
+        b += Upad * ((z / 32 + kZBlockPad - 1) / kZBlockPad * kZBlockPad) * 32 * 8 + tsize * 8;
         if (prec == MODAL_MIXED) b += Upad * z * 8;   // FP32 copy + BF16 split
         *bytes = b;
     });
@@ -804,11 +808,6 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         const int64_t ng = (int64_t)p->ta * p->tp;
         need(c, dgamma != nullptr || ng == 0, MODAL_ERR_INVALID_ARG, "dgamma is NULL");
         need(c, dqk != nullptr || ddelta != nullptr, MODAL_ERR_INVALID_ARG, "dqk and ddelta are both NULL");
-        // The FP64 step-d adjoint streams the dense tensor of dL/dT (U^3
-        // values) once per z chunk; beyond U = 512 that traffic grows past
-        // petabytes.  The mixed adjoint streams it once per z tile.
-        need(c, prec == MODAL_MIXED || d.U <= 512, MODAL_ERR_UNSUPPORTED,
-             "the FP64 adjoint supports np * na <= 512 in this version");
         // inverse maps of the mode lists (ordered: the triple; symmetric: its sorted form)
         std::vector<int> inva((size_t)d.na * d.na * d.na, -1), invp((size_t)d.np * d.np * d.np, -1);
         auto fill = [&](const int32_t *tri, int n, int base, std::vector<int> &inv, const char *which) {
@@ -844,52 +843,35 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
               "H2D");
         hipck(c, hipMemcpyAsync(dinvp, invp.data(), sizeof(int) * invp.size(), hipMemcpyHostToDevice, c->stream),
               "H2D");
-        const int64_t nzb = ldz / 32;
-        double *Shat = nullptr;
+        // pair blocks (v block <= w block) of 16 rows
+        const int nvb = (d.U + 15) / 16, nib = (int)(upad / adj_rowblock());
+        std::vector<int2> pbl;
+        for (int vb = 0; vb < nvb; ++vb)
+            for (int wb = vb; wb < nvb; ++wb) pbl.push_back(make_int2(vb, wb));
+        const int npb = (int)pbl.size();
+        int2 *dpb = (int2 *)ws_get(c, W_PBL, sizeof(int2) * pbl.size());
+        hipck(c, hipMemcpyAsync(dpb, pbl.data(), sizeof(int2) * pbl.size(), hipMemcpyHostToDevice, c->stream),
+              "H2D");
+        // z blocks of the output: whole z tiles of the kernel (St is zero past ldz)
+        const int64_t nzb = ldz / 32, nzbp = (nzb + kZBlockPad - 1) / kZBlockPad * kZBlockPad;
+        double *Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)nzbp * upad * 32);
         if (prec == MODAL_MIXED) {
-            // pair blocks (v block <= w block) of 16 rows; z tiles completed
-            // with zero rows of S
-            const int nvb = (d.U + 15) / 16, nib = (int)(upad / adj_mixed_rowblock());
-            std::vector<int2> pbl;
-            for (int vb = 0; vb < nvb; ++vb)
-                for (int wb = vb; wb < nvb; ++wb) pbl.push_back(make_int2(vb, wb));
-            const int npb = (int)pbl.size();
-            const int64_t nzbp = (nzb + adj_mixed_zblocks() - 1) / adj_mixed_zblocks() * adj_mixed_zblocks();
-            int2 *dpb = (int2 *)ws_get(c, W_Y, sizeof(int2) * pbl.size());
-            hipck(c, hipMemcpyAsync(dpb, pbl.data(), sizeof(int2) * pbl.size(), hipMemcpyHostToDevice, c->stream),
-                  "H2D");
             uint4 *Hc = (uint4 *)ws_get(c, W_H, sizeof(uint4) * (size_t)npb * nib * 8192);
             float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * (size_t)nzbp * upad * 32);
-            Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)nzbp * upad * 32);
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
-            if (ng > 0) {
-                hipck(c, launch_build_hc_mixed(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib, Hc,
-                                               c->stream),
-                      "build Hc");
-            } else {
-                zero(c, (double *)Hc, (int64_t)npb * nib * 8192 * 2);
-            }
-            hipck(c, launch_f32_copy((int64_t)nzb * upad * 32, (int64_t)nzbp * upad * 32, f.St, s32, c->stream),
+            hipck(c, launch_build_hc_mixed(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib, Hc,
+                                           c->stream),
+                  "build Hc");
+            hipck(c, launch_f32_copy((int64_t)nzbp * upad * 32, (int64_t)nzbp * upad * 32, f.St, s32, c->stream),
                   "FP32 copy of S");
             hipck(c, launch_adj_triple_mixed(dpb, npb, d.U, upad, nzbp, s32, Hc, Shat, c->stream), "dL/dS");
         } else {
-            const size_t U3 = (size_t)d.U * d.U * d.U;
-            double *H = (double *)ws_get(c, W_H, sizeof(double) * U3);
-            Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)nzb * upad * 32);
-            const size_t per_z = (size_t)d.U * d.U * sizeof(double);
-            int64_t zc = (int64_t)std::max<size_t>(64, ((size_t)1 << 31) / per_z) / 64 * 64;
-            zc = std::min<int64_t>(zc, (ldz + 63) / 64 * 64);
-            double *Y = (double *)ws_get(c, W_Y, per_z * (size_t)zc);
+            double *Hc = (double *)ws_get(c, W_H, sizeof(double) * (size_t)npb * nib * 32768);
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
-            if (ng > 0)
-                hipck(c, launch_build_h(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, H, c->stream),
-                      "build H");
-            else
-                zero(c, H, (int64_t)U3);
-            for (int64_t z0 = 0; z0 < ldz; z0 += zc) {
-                const int n = (int)std::min<int64_t>(zc, ldz - z0);
-                hipck(c, launch_shat_chunk(d.U, n, z0, upad, H, f.St, Y, Shat, c->stream), "dL/dS");
-            }
+            hipck(c, launch_build_hc_f64(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib, Hc,
+                                         c->stream),
+                  "build Hc");
+            hipck(c, launch_adj_triple_f64(dpb, npb, d.U, upad, nzbp, f.St, Hc, Shat, c->stream), "dL/dS");
         }
         // (c) adjoint
         double *bhat = (double *)ws_get(c, W_BHAT, sizeof(double) * (size_t)d.np * d.L * d.nr);

@@ -100,8 +100,10 @@ struct TriplePlan {
     unsigned short *pair_lk = nullptr; // [ntiles * 16]
     int2 *tasks = nullptr;       // [ntasks] (group, row super-block)
 };
-// S rows are allocated padded to a multiple of kRowPad (>= every rowblock).
+// S rows are allocated padded to a multiple of kRowPad (>= every rowblock),
+// and the z blocks of 32 to a multiple of kZBlockPad (zero past the data).
 constexpr int kRowPad = 256;
+constexpr int kZBlockPad = 8;
 hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group_rows,
                              TriplePlan &plan, std::string &err);
 void free_triple_plan(TriplePlan &plan);
@@ -139,25 +141,23 @@ hipError_t launch_gather_bt(int kind, int ta, int tp, const int *tri_a, const in
 hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *SA,
                              hipStream_t s);
 
-// Adjoint stages (k_adjoint.hip).
-hipError_t launch_build_h(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
-                          const double *G, int tp, double *H, hipStream_t s);
-// dL/dSt (z-blocked like St, upad rows per block) for z in [z0, z0 + zc) from
-// the dense H [U][U][U], through Y[(u,v)][z] = Sum_w H St_w (zc columns)
-hipError_t launch_shat_chunk(int U, int zc, int64_t z0, int64_t upad, const double *H, const double *St,
-                             double *Y, double *Shat, hipStream_t s);
-// Mixed adjoint of step d: Hc in the kernel's operand order from G, for
-// pair blocks pblocks[npb] (16-row v block <= w block) and nib row blocks
+// Adjoint stages (k_adjoint*.hip).  Step d: dL/dSt_u(z) = Sum_{v <= w}
+// Hc[u][(v,w)] St_v(z) St_w(z) over pair blocks pblocks[npb] (16-row v block
+// <= w block) and nib row blocks of adj_rowblock() rows; Hc is built from G
+// in each kernel's operand order.  Shat and St/S32 are z-blocked with nzb z
+// blocks (a multiple of kZBlockPad, zero past the data); rows >= U of Shat
+// are left unwritten.
+int adj_rowblock();
 hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
                                  const double *G, int tp, const int2 *pblocks, int npb, int nib, uint4 *Hc,
                                  hipStream_t s);
-// dL/dSt from Hc and the FP32 rows S32 (z-blocked, nzb z blocks: a multiple
-// of adj_mixed_zblocks(), zero past the data; upad a multiple of
-// adj_mixed_rowblock()); rows >= U of Shat are left unwritten.
 hipError_t launch_adj_triple_mixed(const int2 *pblocks, int npb, int U, int64_t upad, int64_t nzb,
                                    const float *S32, const uint4 *Hc, double *Shat, hipStream_t s);
-int adj_mixed_zblocks();
-int adj_mixed_rowblock();
+hipError_t launch_build_hc_f64(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                               const double *G, int tp, const int2 *pblocks, int npb, int nib, double *Hc,
+                               hipStream_t s);
+hipError_t launch_adj_triple_f64(const int2 *pblocks, int npb, int U, int64_t upad, int64_t nzb,
+                                 const double *St, const double *Hc, double *Shat, hipStream_t s);
 // S32[i] = St[i] for i < n, 0 for n <= i < ntot
 hipError_t launch_f32_copy(int64_t n, int64_t ntot, const double *St, float *S32, hipStream_t s);
 // dL/dbeta from dL/dSt (z-blocked, times wz on read)

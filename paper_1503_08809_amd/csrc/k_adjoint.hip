@@ -7,11 +7,10 @@
 // Step d.  Gamma is a sum of entries of T[u1,u2,u3] = Sum_z St_u1 St_u2 St_u3
 // (St = W^(1/3) S), so with H the symmetric tensor of dL/dT,
 //     dL/dSt_u(z) = 3 Sum_{v,w} H[u,v,w] St_v(z) St_w(z).
-// H is assembled entry by entry from G (each entry gathers the Gamma entries
-// it feeds; no atomics).  The contraction is done per z chunk as
-//     Y[(u,v), z] = Sum_w H[u,v,w] St_w(z)      (FP64 matrix-core GEMM)
-//     dL/dSt_u(z) = 3 Sum_v St_v(z) Y[(u,v), z],
-// and dL/dS = W^(1/3) dL/dSt.
+// Here H is evaluated entry by entry from G (each entry gathers the Gamma
+// entries it feeds; no atomics) straight into the operand order of the
+// block kernels (k_adjoint_f64.hip, k_adjoint_mx.hip) as
+// Hc[u][(v,w)] = 3 c_vw H[u,v,w] over pairs v <= w, and dL/dS = W^(1/3) dL/dSt.
 // Step c.  betahat_p(l, r) = Sum_{a, mu} [w_l qbar_a(l) P_l(mu)] Shat_ap(r, mu):
 //   one GEMM per p with the (a, mu) depth and a generated A operand.
 // Step b.  Ahat_l[p, k] = Sum_r betahat_p(l, r) j_l(k r) per l on regenerated
@@ -76,18 +75,6 @@ __device__ double adj_h(int kind, int np, int na, const int *__restrict__ inv_a,
     return h;
 }
 
-__global__ void k_build_h(int kind, int U, int np, int na, const int *__restrict__ inv_a,
-                          const int *__restrict__ inv_p, const double *__restrict__ G, int tp,
-                          double *__restrict__ H)
-{
-    const int64_t n3 = (int64_t)U * U * U;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int u3 = (int)(e % U), u2 = (int)((e / U) % U), u1 = (int)(e / ((int64_t)U * U));
-        H[e] = adj_h(kind, np, na, inv_a, inv_p, G, tp, u1, u2, u3);
-    }
-}
-
 // Hc[u][(v,w)] = 3 c_vw H[u,v,w] (c = 2 for v < w, 1 for v = w, 0 for v > w)
 // split into BF16 hi and lo, in the A-operand order of the mixed adjoint
 // kernel: Hc[pair block][row block of 128][step][row tile][hi/lo][lane], a
@@ -134,37 +121,28 @@ __global__ void k_build_hc_mx(int kind, int U, int np, int na, const int *__rest
     }
 }
 
-// ---- Y = H St over a z chunk ----------------------------------------------------
-struct YOp {
-    static constexpr bool a_k_fast = true;    // H[(u,v)][w]
-    static constexpr bool b_k_fast = false;   // St z-blocked: z contiguous within 32
-    int M, N, K;                              // U*U, zc, U
-    int64_t z0, upad;
-    const double *H, *St;
-    double *Y;
-    __device__ double a(int, int m, int k) const { return H[(size_t)m * K + k]; }
-    __device__ double bv(int, int k, int n) const
-    {
-        const int64_t z = z0 + n;
-        return St[(((size_t)(z >> 5) * upad + k) << 5) + (z & 31)];
-    }
-    __device__ void store(int, int m, int n, double v) const { Y[(size_t)m * N + n] = v; }
-};
-
-// Shat_u(z) = 3 Sum_v St_v(z) Y[(u,v), z] over the chunk: dL/dSt, z-blocked
-// like St (the W^(1/3) factor is applied where it is read)
-__global__ void k_shat(int U, int zc, int64_t z0, int64_t upad, const double *__restrict__ St,
-                       const double *__restrict__ Y, double *__restrict__ Shat)
+// The same Hc in FP64, in the order of the FP64 adjoint kernel:
+// Hc[pair block][row block of 128][v local][step][row tile][lane], a lane
+// holding row 16-tile + lane % 16 and pair (v local, 4 step + lane / 16).
+__global__ void k_build_hc_f64(int kind, int U, int np, int na, const int *__restrict__ inv_a,
+                               const int *__restrict__ inv_p, const double *__restrict__ G, int tp,
+                               const int2 *__restrict__ pblocks, int npb, int nib, double *__restrict__ Hc)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)U * zc) return;
-    const int u = (int)(i / zc), n = (int)(i % zc);
-    const int64_t z = z0 + n;
-    const double *st = St + ((size_t)(z >> 5) * upad << 5) + (z & 31);
-    const double *y = Y + (size_t)u * U * zc + n;
-    double acc = 0.0;
-    for (int v = 0; v < U; ++v) acc += st[(size_t)v << 5] * y[(size_t)v * zc];
-    Shat[(((size_t)(z >> 5) * upad + u) << 5) + (z & 31)] = 3.0 * acc;
+    const int64_t n = (int64_t)npb * nib * 16 * 4 * 8 * 64;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(e & 63), rt = (int)((e >> 6) & 7), kk = (int)((e >> 9) & 3);
+        const int sv = (int)((e >> 11) & 15);
+        const int64_t pbib = e >> 15;
+        const int ib = (int)(pbib % nib), pb = (int)(pbib / nib);
+        const int2 b = pblocks[pb];
+        const int u = ib * 128 + rt * 16 + (lane & 15);
+        const int v = b.x * 16 + sv, w = b.y * 16 + 4 * kk + (lane >> 4);
+        double h = 0.0;
+        if (u < U && v < U && w < U && v <= w)
+            h = (v < w ? 6.0 : 3.0) * adj_h(kind, np, na, inv_a, inv_p, G, tp, u, v, w);
+        Hc[e] = h;
+    }
 }
 
 // ---- betahat ------------------------------------------------------------------
@@ -232,16 +210,6 @@ __global__ void k_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const doub
 
 }  // namespace
 
-hipError_t launch_build_h(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
-                          const double *G, int tp, double *H, hipStream_t s)
-{
-    const int64_t n3 = (int64_t)U * U * U;
-    const int64_t blocks = std::min<int64_t>((n3 + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL(k_build_h, dim3((unsigned)blocks), dim3(256), 0, s, kind, U, np, na, inv_a, inv_p,
-                       G, tp, H);
-    return hipGetLastError();
-}
-
 hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
                                  const double *G, int tp, const int2 *pblocks, int npb, int nib, uint4 *Hc,
                                  hipStream_t s)
@@ -254,15 +222,15 @@ hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv
     return hipGetLastError();
 }
 
-hipError_t launch_shat_chunk(int U, int zc, int64_t z0, int64_t upad, const double *H, const double *St,
-                             double *Y, double *Shat, hipStream_t s)
+hipError_t launch_build_hc_f64(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                               const double *G, int tp, const int2 *pblocks, int npb, int nib, double *Hc,
+                               hipStream_t s)
 {
-    YOp op{U * U, zc, U, z0, upad, H, St, Y};
-    hipError_t e = run(op, 1, s);
-    if (e != hipSuccess) return e;
-    const int64_t n = (int64_t)U * zc;
-    hipLaunchKernelGGL(k_shat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, zc, z0, upad, St, Y,
-                       Shat);
+    const int64_t n = (int64_t)npb * nib * 16 * 4 * 8 * 64;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_hc_f64, dim3((unsigned)blocks), dim3(256), 0, s, kind, U, np, na, inv_a, inv_p,
+                       G, tp, pblocks, npb, nib, Hc);
     return hipGetLastError();
 }
 

@@ -307,7 +307,6 @@ hipError_t launch_f32_copy(int64_t n, int64_t ntot, const double *St, float *S32
     return hipGetLastError();
 }
 
-int adj_mixed_zblocks() { return ZBW; }
-int adj_mixed_rowblock() { return AI; }
+static_assert(kZBlockPad % ZBW == 0, "z tiles must divide the z-block padding");
 
 }  // namespace mp
