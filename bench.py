@@ -1,26 +1,36 @@
-"""Benchmark of the separable bispectrum projection on one MI355X.
+"""Benchmark of the separable bispectrum projection and its adjoint on one MI355X.
 
-One step = one whole projection (Gauss-Legendre rule, P_l table, j_l and the
-k contraction, the l contraction, the triple-product quadrature and the
-gather of Gamma) over seeded synthetic inputs already resident in HBM.
-Prints ONE JSON line (rank 0).  The default workload is the Planck-like
-case: lmax = 2500, Nk = 2000, Nr = 400, Nmu = 3752, 30 + 30 one-dimensional
-modes, symmetric 4960 x 4960 Gamma.
+One step = one forward projection Gamma (Gauss-Legendre rule, P_l table, j_l
+and the k contraction, the l contraction, the triple-product quadrature, the
+gather of Gamma) followed by its adjoint for the loss L = Sum (Gamma * W)^2
+with W a seeded N(0,1) matrix: dL/dq_p(k) and dL/dDelta_l(k) (j_l tables
+regenerated, not stored).  Inputs are seeded synthetic tables already
+resident in HBM.  Prints ONE JSON line.  The default workload is the
+Planck-like case: lmax = 2500, Nk = 2000, Nr = 400, Nmu = 3752, 30 + 30
+one-dimensional modes, symmetric 4960 x 4960 Gamma, in the mixed precision;
+the FP64 path runs one step beside it for the speed-up and the errors.
 
 Fields beyond the driver contract:
-  roofline      the dominant kernel (the triple-product quadrature) measured
-                with HIP events on the library's stream over the timed steps;
-                achieved = algorithmic FLOPs per launch / mean launch time.
+  roofline      the dominant kernel of the timed path (the adjoint of the
+                triple-product step), measured with HIP events on the
+                library's stream over the timed steps; achieved = algorithmic
+                FLOPs per launch / mean launch time, against the published
+                dense peak of the kernel's matrix-core type.  The split-BF16
+                kernels issue three BF16 products per algorithmic term, so
+                their matrix pipes are busy 3 x frac of the time
+                ("mfma_pipe_frac").
+  roofline_forward  the same for the forward triple-product kernel.
   cpu_baseline  the oracle (plain FP64 C, OpenMP) timed on this host on a
-                bounded sample of the same workload, extrapolated to the
-                whole projection by its exact per-unit costs.
-  paths         per-precision seconds per projection, errors vs the FP64 path.
+                bounded sample of the same workload, extrapolated by its
+                exact per-unit costs.
+  paths         per-precision seconds per step, forward and adjoint
+                separately, per-stage milliseconds, errors vs the FP64 path.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
-import math
 import os
 import sys
 import time
@@ -31,8 +41,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "Γ projection time (s) and MFMA TFLOP/s fraction, mixed vs FP64, at stated rel err"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}
-HBM_GBS = 8000.0
 
 
 def unique_moments(U: int) -> int:
@@ -41,21 +51,31 @@ def unique_moments(U: int) -> int:
 
 
 def algorithmic_flops(cfg) -> dict:
-    """FLOPs the method has to do (an FMA counts 2)."""
-    L, U = cfg.L, cfg.n1 * cfg.n1
-    fb = 2.0 * cfg.n1 * cfg.nk * cfg.nr * L
-    fc = 2.0 * U * cfg.nr * L * cfg.nmu
-    fd = 2.0 * unique_moments(U) * cfg.nr * cfg.nmu
-    return {"beta": fb, "S": fc, "triple": fd, "total": fb + fc + fd}
+    """FLOPs the method has to do (an FMA counts 2), per stage."""
+    L, U, Z = cfg.L, cfg.n1 * cfg.n1, cfg.nr * cfg.nmu
+    f = {
+        "beta": 2.0 * cfg.n1 * cfg.nk * cfg.nr * L,
+        "S": 2.0 * U * cfg.nr * L * cfg.nmu,
+        "triple": 2.0 * unique_moments(U) * Z,
+        # adjoint: every row u against every pair v <= w, per z
+        "adj_triple": 2.0 * U * (U * (U + 1) // 2) * Z,
+        "adj_S": 2.0 * U * cfg.nr * L * cfg.nmu,
+        "adj_beta": 2.0 * cfg.n1 * cfg.nk * cfg.nr * L + 4.0 * cfg.n1 * cfg.nk * L,
+    }
+    f["forward"] = f["beta"] + f["S"] + f["triple"]
+    f["adjoint"] = f["adj_triple"] + f["adj_S"] + f["adj_beta"]
+    f["total"] = f["forward"] + f["adjoint"]
+    return f
 
 
-def cpu_baseline(inp, max_seconds: float = 25.0) -> dict:
+def cpu_baseline(inp, adjoint: bool = True) -> dict:
     """Time the oracle on a bounded sample and extrapolate.
 
-    Sample: the oracle's own stages on a slice of nr_s radial points (the
-    oracle's cost is linear in Nr): beta for every primordial mode, S for a
-    few (a, p) pairs and Gamma for a block of entries.  Each measured per-unit
-    cost is multiplied by the workload's unit count.
+    Sample: the oracle's own stages on a slice of nr_s radial points (every
+    stage's cost is linear in Nr): beta for every primordial mode, S for 9
+    (a, p) pairs and Gamma for 2^16 entries; with the adjoint, the same three
+    adjoint stages on the same sample.  Each measured per-unit cost is
+    multiplied by the workload's unit count.
     """
     from oracle import oracle as O
     from paper_1503_08809_amd import synth
@@ -63,35 +83,44 @@ def cpu_baseline(inp, max_seconds: float = 25.0) -> dict:
     nr_s = max(2, min(c.nr, 16))
     sub = synth.Inputs(c, inp.k, inp.wk, inp.r[:nr_s].copy(), inp.wr[:nr_s].copy(), inp.cl,
                        inp.delta, inp.qk, inp.ql, inp.tri_a, inp.tri_p)
-    import dataclasses
-    sub_cfg = dataclasses.replace(c, nr=nr_s)
-    sub.cfg = sub_cfg
+    sub.cfg = dataclasses.replace(c, nr=nr_s)
+    rscale = c.nr / nr_s
+    U = c.n1 * c.n1
+    t = {}
     t0 = time.perf_counter()
     mu, wmu = O.gauss_legendre(c.nmu)
-    t_gl = time.perf_counter() - t0
+    t["gl"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     bet = O.beta(sub)                                   # every primordial mode
-    t_beta = (time.perf_counter() - t0) * (c.nr / nr_s)
+    t["beta"] = (time.perf_counter() - t0) * rscale
     pairs = [(a, p) for a in range(min(c.n1, 3)) for p in range(min(c.n1, 3))]
     t0 = time.perf_counter()
     S = O.S_pairs(sub, mu, bet, pairs)
-    t_s = (time.perf_counter() - t0) / len(pairs) * (c.n1 * c.n1) * (c.nr / nr_s)
+    t["S"] = (time.perf_counter() - t0) / len(pairs) * U * rscale
     ne = 1 << 16
     rng = np.random.default_rng(0)
     sidx = rng.integers(0, len(pairs), size=(ne, 9)).astype(np.int32)
+    n_entries = inp.tri_a.shape[0] * inp.tri_p.shape[0]
     t0 = time.perf_counter()
     O.gamma_from_S(sub, wmu, S, sidx)
-    t_g1 = time.perf_counter() - t0
-    n_entries = inp.tri_a.shape[0] * inp.tri_p.shape[0]
-    t_d = t_g1 / ne * n_entries * (c.nr / nr_s)
-    total = t_gl + t_beta + t_s + t_d
-    return {
-        "value": total, "unit": "s (extrapolated)", "cores": O.num_threads(), "kind": "oracle",
-        "sample": (f"oracle stages on {nr_s} of {c.nr} r points: beta for all modes, "
-                   f"S for {len(pairs)} of {c.n1 * c.n1} (a,p) pairs, {ne} of {n_entries} "
-                   "Gamma entries; per-unit costs x unit counts (cost is linear in each)"),
-        "stages_s": {"gl": t_gl, "beta": t_beta, "S": t_s, "gamma": t_d},
-    }
+    t["gamma"] = (time.perf_counter() - t0) / ne * n_entries * rscale
+    sample = (f"oracle stages on {nr_s} of {c.nr} r points: beta for all modes, "
+              f"S for {len(pairs)} of {U} (a,p) pairs, {ne} of {n_entries} Gamma entries")
+    if adjoint:
+        g = rng.standard_normal(ne)
+        t0 = time.perf_counter()
+        Shat = O.gamma_adjoint_S(sub, wmu, S, sidx, g)
+        t["adj_gamma"] = (time.perf_counter() - t0) / ne * n_entries * rscale
+        t0 = time.perf_counter()
+        bhat = O.S_adjoint(sub, mu, Shat, np.array(pairs, dtype=np.int32), c.n1)
+        t["adj_S"] = (time.perf_counter() - t0) / len(pairs) * U * rscale
+        t0 = time.perf_counter()
+        O.beta_adjoint(sub, bhat)
+        t["adj_beta"] = (time.perf_counter() - t0) * rscale
+        sample += "; the three adjoint stages on the same sample"
+    sample += "; per-unit costs x unit counts (cost is linear in each)"
+    return {"value": sum(t.values()), "unit": "s (extrapolated)", "cores": O.num_threads(),
+            "kind": "oracle", "sample": sample, "stages_s": t}
 
 
 def main() -> int:
@@ -101,7 +130,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3, help="workload 1..5")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--forward-only", action="store_true", help="time Gamma without the adjoint")
+    ap.add_argument("--no-fp64-ref", action="store_true",
+                    help="skip the FP64 reference step (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -120,65 +154,127 @@ def main() -> int:
     ctx = mp.Context(0)
     pr = mp.projection_from_inputs(ctx, inp)
     out = ctx.empty(inp.tri_a.shape[0], inp.tri_p.shape[0])
+    W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    W2 = 2.0 * W * W
     flops = algorithmic_flops(cfg)
+    adjoint = not args.forward_only
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 17                     # doubles
+        src = torch.ones(n, dtype=torch.float64, device=ctx.torch_device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {n * 8} bytes read, {n * 8} bytes written",
+              file=sys.stderr, flush=True)
+        del src, dst
+
+    def one_step(prec: str, timed: bool):
+        ta = time.perf_counter()
+        pr.gamma(prec, out=out)
+        sf = ctx.stage_times() if timed else None          # waits for the stream
+        if not timed:
+            torch.cuda.synchronize()
+        tb = time.perf_counter()
+        grads, sb = None, None
+        if adjoint:
+            grads = pr.gamma_backward(out * W2, prec)
+            sb = ctx.stage_times() if timed else None
+            if not timed:
+                torch.cuda.synchronize()
+        tc = time.perf_counter()
+        return tb - ta, tc - tb, sf, sb, grads
 
     def run_path(prec: str, steps: int, warmup: int):
         ctx.enable_timing(False)
         for _ in range(warmup):
-            pr.gamma(prec, out=out)
+            one_step(prec, False)
         torch.cuda.synchronize()
         ctx.enable_timing(True)
-        stage_sum = {}
+        acc = {"fwd": 0.0, "adj": 0.0}
+        stf, stb = {}, {}
+        grads = None
         t_start = time.perf_counter()
         for s in range(steps):
-            pr.gamma(prec, out=out)
-            st = ctx.stage_times()          # waits for the stream
-            for kname, v in st.items():
-                stage_sum[kname] = stage_sum.get(kname, 0.0) + v
-            print(f"[bench] {prec} step {s + 1}/{steps} done", file=sys.stderr, flush=True)
+            tf, tb, sf, sb, grads = one_step(prec, True)
+            acc["fwd"] += tf
+            acc["adj"] += tb
+            for src, dst in ((sf, stf), (sb, stb)):
+                for kname, v in (src or {}).items():
+                    if v:
+                        dst[kname] = dst.get(kname, 0.0) + v
+            print(f"[bench] {prec} step {s + 1}/{steps}: forward {tf:.3f} s, adjoint {tb:.3f} s",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         ctx.enable_timing(False)
-        return elapsed / steps, {k: v / steps for k, v in stage_sum.items()}
+        res = {"s_per_step": elapsed / steps, "forward_s": acc["fwd"] / steps,
+               "adjoint_s": acc["adj"] / steps,
+               "stage_ms_forward": {k: v / steps for k, v in stf.items()},
+               "stage_ms_adjoint": {k: v / steps for k, v in stb.items()}}
+        return res, grads
+
+    def nerr(a, b):
+        return float((a - b).abs().max() / b.abs().max())
 
     paths = {}
-    sec64, st64 = run_path("fp64", args.steps if args.precision == "fp64" else 1,
-                           args.warmup if args.precision == "fp64" else 0)
-    g64 = out.clone()
-    paths["fp64"] = {"s_per_projection": sec64, "stage_ms": st64}
     main_prec = args.precision
+    ref = None
+    if main_prec == "fp64" or not args.no_fp64_ref:
+        fp_steps = args.steps if main_prec == "fp64" else 1
+        fp_warm = args.warmup if main_prec == "fp64" else 0
+        paths["fp64"], g64 = run_path("fp64", fp_steps, fp_warm)
+        ref = (out.clone(), g64)
     if main_prec == "mixed":
-        secm, stm = run_path("mixed", args.steps, args.warmup)
-        err = float((out - g64).abs().max() / g64.abs().max())
-        paths["mixed"] = {"s_per_projection": secm, "stage_ms": stm,
-                          "normwise_err_vs_fp64": err, "speedup_vs_fp64": sec64 / secm}
-    sec, stages = paths[main_prec]["s_per_projection"], paths[main_prec]["stage_ms"]
+        paths["mixed"], gm = run_path("mixed", args.steps, args.warmup)
+        if ref is not None:
+            m = paths["mixed"]
+            m["gamma_normwise_err_vs_fp64"] = nerr(out, ref[0])
+            if adjoint:
+                m["dq_normwise_err_vs_fp64"] = nerr(gm[0], ref[1][0])
+                m["ddelta_normwise_err_vs_fp64"] = nerr(gm[1], ref[1][1])
+            f64 = paths["fp64"]
+            m["speedup_vs_fp64"] = f64["s_per_step"] / m["s_per_step"]
+            m["forward_speedup_vs_fp64"] = f64["forward_s"] / m["forward_s"]
+            if adjoint:
+                m["adjoint_speedup_vs_fp64"] = f64["adjoint_s"] / m["adjoint_s"]
+    main = paths[main_prec]
+    sec = main["s_per_step"]
 
-    triple_ms = stages["triple"]
-    achieved = flops["triple"] / (triple_ms * 1e-3) / 1e12
     if main_prec == "fp64":
-        peak, dt = PEAK_TFLOPS["fp64"], "f64"
+        peak, dt, pipe = PEAK_TFLOPS["fp64"], "f64", 1.0
     else:
-        peak, dt = PEAK_TFLOPS["bf16"] / 3.0, "bf16x3+f32acc+f64"
-    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "kernel": "k_triple",
-            "flops_per_launch": flops["triple"], "mean_launch_ms": triple_ms}
+        peak, dt, pipe = PEAK_TFLOPS["bf16"], "bf16x3+f32acc+f64", 3.0
+
+    def roof(kernel: str, stage: str, ms: float) -> dict:
+        achieved = flops[stage] / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "mfma_pipe_frac": pipe * achieved / peak, "traffic": None,
+                "kernel": kernel, "flops_per_launch": flops[stage], "mean_launch_ms": ms}
+
+    kfwd = "k_triple_bt" if main_prec == "mixed" else "k_triple_f64"
+    kadj = "k_adj_bt" if main_prec == "mixed" else "k_adj_f64"
+    r_fwd = roof(kfwd, "triple", main["stage_ms_forward"]["triple"])
+    r_adj = roof(kadj, "adj_triple", main["stage_ms_adjoint"]["adj_triple"]) if adjoint else None
+    dominant = r_adj if adjoint and r_adj["mean_launch_ms"] > r_fwd["mean_launch_ms"] else r_fwd
 
     line = {
-        "metric": "Gamma projection time (s) at lmax=2500 and MFMA TFLOP/s fraction",
+        "metric": METRIC,
         "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "strong",
         "vs_baseline": None, "dtype": dt, "data": "synthetic",
-        "config": {"workload": cfg.name, "lmax": cfg.lmax, "nk": cfg.nk, "nr": cfg.nr,
-                   "nmu": cfg.nmu, "n1": cfg.n1, "kind": cfg.kind, "precision": main_prec,
-                   "gamma_shape": list(out.shape)},
-        "algorithmic_tflop": flops["total"] / 1e12,
-        "achieved_tflops_total": flops["total"] / sec / 1e12,
-        "roofline": roof,
+        "config": {"workload": cfg.name + ("_forward" if not adjoint else "_forward_adjoint"),
+                   "lmax": cfg.lmax, "nk": cfg.nk, "nr": cfg.nr, "nmu": cfg.nmu, "n1": cfg.n1,
+                   "kind": cfg.kind, "precision": main_prec, "gamma_shape": list(out.shape),
+                   "loss": "sum((Gamma * W)^2), W seeded N(0,1)" if adjoint else None},
+        "algorithmic_tflop": (flops["total"] if adjoint else flops["forward"]) / 1e12,
+        "achieved_tflops_total": (flops["total"] if adjoint else flops["forward"]) / sec / 1e12,
+        "roofline": dominant,
+        "roofline_forward": r_fwd,
         "paths": paths,
     }
     if not args.no_cpu:
-        cb = cpu_baseline(inp)
+        cb = cpu_baseline(inp, adjoint)
         cb["gpu_speedup"] = cb["value"] / sec
         line["cpu_baseline"] = cb
     else:

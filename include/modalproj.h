@@ -145,12 +145,16 @@ modal_status modal_workspace_bytes(modal_ctx ctx, const modal_grid *grid,
 /* Stage timing.  When enabled, each later call records HIP events around
  * its kernels on the context's stream; modal_stage_times then waits for the
  * stream and reports the milliseconds of the last call's stages, in order
- * MODAL_STAGE_GL, _LEGENDRE, _BESSEL, _BETA, _S, _TRIPLE, _GATHER and the
- * adjoint's _ADJ_TRIPLE, _ADJ_S, _ADJ_BETA (0 for a stage the call did not
- * run).  n is the length of ms (>= MODAL_NSTAGES). */
+ * MODAL_STAGE_GL, _LEGENDRE, _BESSEL, _BETA, _S, _TRIPLE, _GATHER, the
+ * adjoint's _ADJ_TRIPLE, _ADJ_S, _ADJ_BETA, then _PREP (operand conversion
+ * before the mixed triple product) and _ADJ_PREP (the adjoint's operand
+ * assembly before _ADJ_TRIPLE); 0 for a stage the call did not run.  The
+ * _TRIPLE and _ADJ_TRIPLE times cover the triple-product kernels alone.
+ * n is the length of ms (>= MODAL_NSTAGES). */
 enum { MODAL_STAGE_GL = 0, MODAL_STAGE_LEGENDRE, MODAL_STAGE_BESSEL, MODAL_STAGE_BETA,
        MODAL_STAGE_S, MODAL_STAGE_TRIPLE, MODAL_STAGE_GATHER,
-       MODAL_STAGE_ADJ_TRIPLE, MODAL_STAGE_ADJ_S, MODAL_STAGE_ADJ_BETA, MODAL_NSTAGES };
+       MODAL_STAGE_ADJ_TRIPLE, MODAL_STAGE_ADJ_S, MODAL_STAGE_ADJ_BETA,
+       MODAL_STAGE_PREP, MODAL_STAGE_ADJ_PREP, MODAL_NSTAGES };
 modal_status modal_enable_timing(modal_ctx ctx, int on);
 modal_status modal_stage_times(modal_ctx ctx, double *ms, int n);
 

@@ -501,8 +501,11 @@ void run_triple_gather(modal_ctx c, const modal_problem *p, const Dims &d, modal
     float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * n);
     uint16_t *sa = (uint16_t *)ws_get(c, W_SH, 2 * sizeof(uint16_t) * n);
     {
-        StageTimer tm(c, MODAL_STAGE_TRIPLE);
+        StageTimer tm(c, MODAL_STAGE_PREP);
         hipck(c, launch_split_bf16((int64_t)n, St, s32, sa, c->stream), "split");
+    }
+    {
+        StageTimer tm(c, MODAL_STAGE_TRIPLE);
         hipck(c, launch_triple_bt(plan, upad, ldz, d.ldmu, s32, sa, T, c->stream), "triple mixed");
     }
     if ((int64_t)p->ta * p->tp == 0) return;
@@ -858,19 +861,26 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         if (prec == MODAL_MIXED) {
             uint4 *Hc = (uint4 *)ws_get(c, W_H, sizeof(uint4) * (size_t)npb * nib * 8192);
             float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * (size_t)nzbp * upad * 32);
+            {
+                StageTimer tm(c, MODAL_STAGE_ADJ_PREP);
+                hipck(c, launch_build_hc_mixed(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib,
+                                               Hc, c->stream),
+                      "build Hc");
+                hipck(c, launch_f32_copy((int64_t)nzbp * upad * 32, (int64_t)nzbp * upad * 32, f.St, s32,
+                                         c->stream),
+                      "FP32 copy of S");
+            }
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
-            hipck(c, launch_build_hc_mixed(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib, Hc,
-                                           c->stream),
-                  "build Hc");
-            hipck(c, launch_f32_copy((int64_t)nzbp * upad * 32, (int64_t)nzbp * upad * 32, f.St, s32, c->stream),
-                  "FP32 copy of S");
             hipck(c, launch_adj_triple_mixed(dpb, npb, d.U, upad, nzbp, s32, Hc, Shat, c->stream), "dL/dS");
         } else {
             double *Hc = (double *)ws_get(c, W_H, sizeof(double) * (size_t)npb * nib * 32768);
+            {
+                StageTimer tm(c, MODAL_STAGE_ADJ_PREP);
+                hipck(c, launch_build_hc_f64(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib, Hc,
+                                             c->stream),
+                      "build Hc");
+            }
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
-            hipck(c, launch_build_hc_f64(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib, Hc,
-                                         c->stream),
-                  "build Hc");
             hipck(c, launch_adj_triple_f64(dpb, npb, d.U, upad, nzbp, f.St, Hc, Shat, c->stream), "dL/dS");
         }
         // (c) adjoint

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libmodalproj.so")
 MODAL_FP64, MODAL_MIXED = 0, 1
 ORDERED, SYMMETRIC = 0, 1
 STAGES = ("gl", "legendre", "bessel", "beta", "S", "triple", "gather",
-          "adj_triple", "adj_S", "adj_beta")
+          "adj_triple", "adj_S", "adj_beta", "prep", "adj_prep")
 _PREC = {"fp64": MODAL_FP64, "mixed": MODAL_MIXED}
 _KIND = {"ordered": ORDERED, "symmetric": SYMMETRIC}
 

@@ -180,3 +180,43 @@ def test_config4_finite_differences_and_mixed(mp, ctx):
     eq, ed = normwise(_np(mq), dq), normwise(_np(md), dd)
     print(f"mixed gradient normwise error: dq {eq:.3e}, ddelta {ed:.3e}")
     assert eq <= 1e-4 and ed <= 1e-4
+
+
+def test_config3_gradient_full_size(mp, ctx):
+    """lmax = 2500, 4960 x 4960 symmetric Gamma, L = Sum (Gamma * W)^2.
+
+    Gamma is cubic in q and cubic in Delta (beta is linear in each), so L is
+    homogeneous of degree 6 in each: <dL/dq, q> = 6 L and <dL/dDelta, Delta>
+    = 6 L exactly (Euler).  Also a central difference of the FP64 forward
+    along a seeded direction (relative step 1e-4 in every q and Delta entry;
+    truncation ~1e-7 relative), and the mixed gradient against the FP64 one."""
+    cfg = synth.CONFIGS[3]
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))
+
+    def loss(prj, prec="fp64"):
+        G = prj.gamma(prec)
+        return float(((G * W) ** 2).sum()), G
+
+    L0, G = loss(pr)
+    dq, dd = pr.gamma_backward(2 * G * W * W)
+    e_q = float((dq * pr.qk).sum()) / (6 * L0) - 1
+    e_d = float((dd * pr.delta).sum()) / (6 * L0) - 1
+    print(f"FP64 Euler identities at lmax=2500: {e_q:.2e}, {e_d:.2e}")
+    assert abs(e_q) <= 1e-9 and abs(e_d) <= 1e-9
+    rng = np.random.default_rng(2500)
+    xq = ctx.to_dev(rng.standard_normal(tuple(pr.qk.shape))) * pr.qk * 1e-4
+    xd = ctx.to_dev(rng.standard_normal(tuple(pr.delta.shape))) * pr.delta * 1e-4
+    Lp = loss(mp.projection_from_inputs(ctx, inp, qk=pr.qk + xq, delta=pr.delta + xd))[0]
+    Lm = loss(mp.projection_from_inputs(ctx, inp, qk=pr.qk - xq, delta=pr.delta - xd))[0]
+    lin_q, lin_d = float((dq * xq).sum()), float((dd * xd).sum())
+    fd = (Lp - Lm) / 2
+    print(f"directional derivative: fd {fd:.6e}, adjoint {lin_q + lin_d:.6e} (q {lin_q:.3e}, Delta {lin_d:.3e})")
+    assert abs(fd - (lin_q + lin_d)) <= 1e-6 * (abs(lin_q) + abs(lin_d))
+    Lm_, Gm = loss(pr, "mixed")
+    mq, md = pr.gamma_backward(2 * Gm * W * W, "mixed")
+    eq, ed = normwise(_np(mq), _np(dq)), normwise(_np(md), _np(dd))
+    em_q = float((mq * pr.qk).sum()) / (6 * Lm_) - 1
+    print(f"mixed vs FP64 gradient at lmax=2500: dq {eq:.2e}, ddelta {ed:.2e}; mixed Euler {em_q:.2e}")
+    assert eq <= 1e-4 and ed <= 1e-4 and abs(em_q) <= 1e-5
