@@ -68,6 +68,33 @@ def algorithmic_flops(cfg) -> dict:
     return f
 
 
+KERNEL_SOURCES = {"k_adj_bt": "k_adjoint_mx.hip", "k_triple_bt": "k_triple_mx.hip",
+                  "k_adj_f64": "k_adjoint_f64.hip", "k_triple_f64": "k_triple.hip"}
+
+
+def measured_traffic(kernel: str, tag: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary profiles/<tag>_hbm_traffic.txt (FETCH_SIZE and WRITE_SIZE scaled
+    by the copy-kernel calibration recorded there), or None when there is no
+    such record or the kernel's source has changed since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{tag}_hbm_traffic.txt")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+        return None
+    src = os.path.join(ROOT, "paper_1503_08809_amd", "csrc", KERNEL_SOURCES[kernel])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    ff = wf = None
+    for line in open(path):
+        f = line.split()
+        if f[:1] == ["calibration"]:
+            ff, wf = float(f[2]), float(f[4])
+        elif f[:2] == ["traffic", kernel] and ff is not None:
+            if f[5] != sha:
+                return None
+            return (float(f[2]) * ff + float(f[3]) * wf) * 1024.0
+    return None
+
+
 def cpu_baseline(inp, adjoint: bool = True) -> dict:
     """Time the oracle on a bounded sample and extrapolate.
 
@@ -246,10 +273,13 @@ def main() -> int:
     else:
         peak, dt, pipe = PEAK_TFLOPS["bf16"], "bf16x3+f32acc+f64", 3.0
 
+    tag = f"{main_prec}_lmax{cfg.lmax}"
+
     def roof(kernel: str, stage: str, ms: float) -> dict:
         achieved = flops[stage] / (ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "mfma_pipe_frac": pipe * achieved / peak, "traffic": None,
+                "frac": achieved / peak, "mfma_pipe_frac": pipe * achieved / peak,
+                "traffic": measured_traffic(kernel, tag), "traffic_unit": "bytes per launch",
                 "kernel": kernel, "flops_per_launch": flops[stage], "mean_launch_ms": ms}
 
     kfwd = "k_triple_bt" if main_prec == "mixed" else "k_triple_f64"
