@@ -33,6 +33,7 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 constexpr int AI = 128;            // output rows per workgroup
 constexpr int PB = 16;             // pair block: 16 v x 16 w
@@ -50,10 +51,15 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_s_barrier();
 }
 
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f)
+// x = hi + lo for two values a, b: hi and lo are BF16 roundings to nearest
+// even (v_cvt_pk_bf16_f32), packed as (a, b) halves of h and l.
+__device__ __forceinline__ void split2(float a, float b, uint32_t &h, uint32_t &l)
 {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const bf2 hv = {(__bf16)a, (__bf16)b};
+    h = __builtin_bit_cast(uint32_t, hv);
+    asm("" : "+v"(h));                        // keep one conversion: unpack h itself below
+    const bf2 lv = {(__bf16)(a - __uint_as_float(h << 16)), (__bf16)(b - __uint_as_float(h & 0xffff0000u))};
+    l = __builtin_bit_cast(uint32_t, lv);
 }
 
 __device__ __forceinline__ bf8 as_bf8(uint4 v)
@@ -105,72 +111,62 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
     // float4, four per thread.  v rows (i = 0, 1): a wave covers one row's
     // 256 z (contiguous LDS writes); w rows (i = 2, 3): consecutive lanes take
     // consecutive rows, so the transposed LDS writes spread over the banks.
-    f4 sreg[4];
-    auto sload = [&](int pb) {
+    // part i (0..3) of pair block pb: one float4 per thread
+    auto sload1 = [&](int pb, int i) -> f4 {
         const int2 b = A.pblocks[pb];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = t + 512 * (i & 1);
-            int grow, z4;
-            if (i < 2) { grow = b.x * PB + (f >> 6); z4 = f & 63; }
-            else       { grow = b.y * PB + (f & 15); z4 = f >> 4; }
-            sreg[i] = *reinterpret_cast<const f4 *>(S32 + (((zb0 + (z4 >> 3)) * A.upad + grow) << 5) +
-                                                    4 * (z4 & 7));
-        }
+        const int f = t + 512 * (i & 1);
+        int grow, z4;
+        if (i < 2) { grow = b.x * PB + (f >> 6); z4 = f & 63; }
+        else       { grow = b.y * PB + (f & 15); z4 = f >> 4; }
+        return *reinterpret_cast<const f4 *>(S32 + (((zb0 + (z4 >> 3)) * A.upad + grow) << 5) + 4 * (z4 & 7));
     };
-    auto sstore = [&](int sb) {
+    auto sstore1 = [&](int sb, int i, f4 v) {
+        const int f = t + 512 * (i & 1);
+        if (i < 2) {
+            *reinterpret_cast<f4 *>(&SrcJ[sb][f >> 6][4 * (f & 63)]) = v;
+        } else {
+            const int zl = 4 * (f >> 4), row = f & 15;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = t + 512 * (i & 1);
-            if (i < 2) {
-                *reinterpret_cast<f4 *>(&SrcJ[sb][f >> 6][4 * (f & 63)]) = sreg[i];
-            } else {
-                const int zl = 4 * (f >> 4), row = f & 15;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) SrcK[sb][zl + e][row] = sreg[i][e];
-            }
+            for (int e = 0; e < 4; ++e) SrcK[sb][zl + e][row] = v[e];
         }
     };
     // ---- operand of step ks of the pair block staged in SrcJ/K[sb]: column
     // tiles 2 wave, 2 wave + 1.  Lane: z = tile * 16 + lane % 16, v local =
     // 2 ks + lane / 32, w local = 8 ((lane / 16) % 2) + e (matrix-core depth
-    // index 8 (lane / 16) + e of the step)
-    auto bgen = [&](int sb, int ks, int bb) {
+    // index 8 (lane / 16) + e of the step).  The LDS reads are issued early
+    // (gread) and the products formed later (gwrite), under matrix-core work.
+    float gsv;
+    f4 gw0, gw1;
+    auto gread = [&](int sb, int ks, int q) {
         const int vl = 2 * ks + (lane >> 5), wh = ((lane >> 4) & 1) * 8;
+        const int zl = (2 * wave + q) * 16 + (lane & 15);
+        gsv = SrcJ[sb][vl][zl];
+        gw0 = *reinterpret_cast<const f4 *>(&SrcK[sb][zl][wh]);
+        gw1 = *reinterpret_cast<const f4 *>(&SrcK[sb][zl][wh + 4]);
+    };
+    auto gwrite = [&](int q, int bb) {
+        float v[8];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int ct = 2 * wave + q, zl = ct * 16 + (lane & 15);
-            const float sv = SrcJ[sb][vl][zl];
-            const f4 w0 = *reinterpret_cast<const f4 *>(&SrcK[sb][zl][wh]);
-            const f4 w1 = *reinterpret_cast<const f4 *>(&SrcK[sb][zl][wh + 4]);
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v[e] = sv * w0[e];
-                v[4 + e] = sv * w1[e];
-            }
-            uint32_t h[4], l[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t h0 = bf16_rne_bits(v[2 * e]), h1 = bf16_rne_bits(v[2 * e + 1]);
-                const float r0 = v[2 * e] - __uint_as_float(h0 << 16);
-                const float r1 = v[2 * e + 1] - __uint_as_float(h1 << 16);
-                h[e] = h0 | (h1 << 16);
-                l[e] = bf16_rne_bits(r0) | (bf16_rne_bits(r1) << 16);
-            }
-            Bb[bb][ct][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
-            Bb[bb][ct][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
+        for (int e = 0; e < 4; ++e) {
+            v[e] = gsv * gw0[e];
+            v[4 + e] = gsv * gw1[e];
         }
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], h[e], l[e]);
+        const int ct = 2 * wave + q;
+        Bb[bb][ct][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
+        Bb[bb][ct][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
     };
     // ---- A fragments (Hc) of step (pb, ks) for this wave's two row tiles:
-    // Hc[pb][ib][ks][row tile][hi/lo][lane]
-    uint4 ah[2], al[2];
-    auto aload = [&](int pb, int ks) {
+    // Hc[pb][ib][ks][row tile][hi/lo][lane]; loaded one step ahead
+    uint4 ah[2], al[2], nah[2], nal[2];
+    auto aload = [&](int pb, int ks, uint4 (&h)[2], uint4 (&l)[2]) {
         const uint4 *p = Hc + ((((size_t)pb * A.nib + ib) * KS + ks) * 8 + 2 * rg) * 128 + lane;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            ah[i] = p[i * 128];
-            al[i] = p[i * 128 + 64];
+            h[i] = p[i * 128];
+            l[i] = p[i * 128 + 64];
         }
     };
 
@@ -206,13 +202,21 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
     const int npb = A.npb;
     // prologue: sources of pair block 0, operand of step (0, 0), A of (0, 0),
     // and the loads of pair block 1's sources
-    sload(0);
-    sstore(0);
+    {
+        f4 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = sload1(0, i);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sstore1(0, i, v[i]);
+    }
     lds_barrier();
-    bgen(0, 0, 0);
-    aload(0, 0);
-    sload(npb > 1 ? 1 : 0);
+    gread(0, 0, 0);
+    gwrite(0, 0);
+    gread(0, 0, 1);
+    gwrite(1, 0);
+    aload(0, 0, ah, al);
     lds_barrier();
+    f4 sreg = f4{0.f, 0.f, 0.f, 0.f};
 
     int since_flush = 0;
     bool first = true;
@@ -225,16 +229,26 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
             const bool last_step = ks == KS - 1;
             const int nsb = last_step ? sb ^ 1 : sb, nks = last_step ? 0 : ks + 1;
             const bool has_next = !(last_step && pb + 1 == npb);
+            // A fragments of the next step, a whole step ahead of their use
+            if (has_next) aload(last_step ? pb + 1 : pb, nks, nah, nal);
             if (active) {
-                uint4 bh = Bb[bb][ch * 8][0][lane], bl = Bb[bb][ch * 8][1][lane];
+                // B fragments two tiles ahead of their matrix-core use
+                uint4 bh[3], bl[3];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    bh[j] = Bb[bb][ch * 8 + j][0][lane];
+                    bl[j] = Bb[bb][ch * 8 + j][1][lane];
+                }
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    uint4 nbh = bh, nbl = bl;
-                    if (j + 1 < 8) {
-                        nbh = Bb[bb][ch * 8 + j + 1][0][lane];
-                        nbl = Bb[bb][ch * 8 + j + 1][1][lane];
+                    if (j + 2 < 8) {
+                        bh[(j + 2) % 3] = Bb[bb][ch * 8 + j + 2][0][lane];
+                        bl[(j + 2) % 3] = Bb[bb][ch * 8 + j + 2][1][lane];
                     }
-                    const bf8 h8 = as_bf8(bh), l8 = as_bf8(bl);
+                    // operand of the next step, one tile at a time: LDS reads
+                    // three matrix-core groups before the products
+                    if (has_next && (j == 0 || j == 3)) gread(nsb, nks, j / 3);
+                    const bf8 h8 = as_bf8(bh[j % 3]), l8 = as_bf8(bl[j % 3]);
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), h8, acc[i][j], 0, 0, 0);
@@ -244,27 +258,33 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), h8, acc[i][j], 0, 0, 0);
-                    if (j == 3 && has_next) bgen(nsb, nks, bb ^ 1);     // operand of the next step
+                    if (has_next && (j == 2 || j == 5)) gwrite(j / 3, bb ^ 1);
                     __builtin_amdgcn_sched_barrier(0);
-                    bh = nbh;
-                    bl = nbl;
                 }
             } else if (has_next) {
-                bgen(nsb, nks, bb ^ 1);
+                gread(nsb, nks, 0);
+                gwrite(0, bb ^ 1);
+                gread(nsb, nks, 1);
+                gwrite(1, bb ^ 1);
             }
-            // sources of pair block pb + 1 into the other buffer (free since
-            // the operand of this block's step 0 was generated), and the loads
-            // of pair block pb + 2's sources
-            if (ks == KS / 2) {
-                sstore(sb ^ 1);
-                sload(pb + 2 < npb ? pb + 2 : npb - 1);
+            // sources of pair block pb + 1 into the other buffer (its last
+            // reader formed this block's first operand): one float4 per thread
+            // per step, loaded in steps 0..3 and stored one step later, so they
+            // are visible well before step KS - 1 forms the next block's operand
+            if (pb + 1 < npb) {
+                if (ks >= 1 && ks <= 4) sstore1(sb ^ 1, ks - 1, sreg);
+                if (ks <= 3) sreg = sload1(pb + 1, ks);
             }
             if (last_step && (++since_flush == kFlush || pb + 1 == npb)) {
                 if (active) flush(first);
                 since_flush = 0;
                 first = false;
             }
-            if (has_next) aload(last_step ? pb + 1 : pb, nks);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ah[i] = nah[i];
+                al[i] = nal[i];
+            }
             lds_barrier();
         }
     }

@@ -40,6 +40,7 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 constexpr int BI = 128, BJ = 16, BK = 16;     // rows per task along i, j, k
 constexpr int RB = 2;                         // 16-row blocks per wave
@@ -56,10 +57,15 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_s_barrier();
 }
 
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f)
+// x = hi + lo for two values a, b: hi and lo are BF16 roundings to nearest
+// even (v_cvt_pk_bf16_f32), packed as (a, b) halves of h and l.
+__device__ __forceinline__ void split2(float a, float b, uint32_t &h, uint32_t &l)
 {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const bf2 hv = {(__bf16)a, (__bf16)b};
+    h = __builtin_bit_cast(uint32_t, hv);
+    asm("" : "+v"(h));                        // keep one conversion: unpack h itself below
+    const bf2 lv = {(__bf16)(a - __uint_as_float(h << 16)), (__bf16)(b - __uint_as_float(h & 0xffff0000u))};
+    l = __builtin_bit_cast(uint32_t, lv);
 }
 
 __device__ __forceinline__ bf8 as_bf8(uint4 v)
@@ -157,15 +163,9 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
             v[e] = j0v[e] * k0v[e];
             v[4 + e] = j1v[e] * k1v[e];
         }
-        uint32_t h[4], l[4];
+            uint32_t h[4], l[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const uint32_t h0 = bf16_rne_bits(v[2 * e]), h1 = bf16_rne_bits(v[2 * e + 1]);
-            const float r0 = v[2 * e] - __uint_as_float(h0 << 16);
-            const float r1 = v[2 * e + 1] - __uint_as_float(h1 << 16);
-            h[e] = h0 | (h1 << 16);
-            l[e] = bf16_rne_bits(r0) | (bf16_rne_bits(r1) << 16);
-        }
+            for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], h[e], l[e]);
         Bb[buf][tile][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
         Bb[buf][tile][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
     };

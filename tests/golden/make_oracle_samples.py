@@ -1,0 +1,50 @@
+"""Write oracle values of sampled Gamma entries at the large workloads.
+
+Gamma entries at lmax = 2500 and lmax = 4000 take the oracle minutes to
+compute, too long for a GPU test run, so they are computed here, once, by
+the oracle alone (oracle/ and the seeded input generator; nothing from the
+HIP path) and stored as text: one line per entry, "row col value" with the
+value printed to 17 significant digits.
+
+    python tests/golden/make_oracle_samples.py [config ...]
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O                      # noqa: E402
+from paper_1503_08809_amd import synth               # noqa: E402
+
+COUNT = {3: 8, 5: 6}
+SEED_OFFSET = 11
+
+
+def path_for(ci: int) -> str:
+    return os.path.join(HERE, f"oracle_gamma_{synth.CONFIGS[ci].name}.txt")
+
+
+def main(cfgs):
+    for ci in cfgs:
+        cfg = synth.CONFIGS[ci]
+        inp = synth.make_inputs(cfg)
+        shape = (inp.tri_a.shape[0], inp.tri_p.shape[0])
+        idx = synth.pick_entries(cfg, shape, COUNT[ci], seed_offset=SEED_OFFSET)
+        rows, cols = np.unravel_index(idx, shape)
+        vals = O.gamma_entries(inp, rows, cols)
+        with open(path_for(ci), "w") as f:
+            f.write(f"# oracle Gamma entries, workload {cfg.name} (Gamma {shape[0]} x {shape[1]}),\n")
+            f.write(f"# {COUNT[ci]} seeded entries (synth.pick_entries, seed offset {SEED_OFFSET});\n")
+            f.write("# written by tests/golden/make_oracle_samples.py from the oracle only\n")
+            f.write("# row col value\n")
+            for r, c, v in zip(rows, cols, vals):
+                f.write(f"{r} {c} {v:.17g}\n")
+        print("wrote", path_for(ci), flush=True)
+
+
+if __name__ == "__main__":
+    main([int(a) for a in sys.argv[1:]] or [3, 5])

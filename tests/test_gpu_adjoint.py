@@ -220,3 +220,21 @@ def test_config3_gradient_full_size(mp, ctx):
     em_q = float((mq * pr.qk).sum()) / (6 * Lm_) - 1
     print(f"mixed vs FP64 gradient at lmax=2500: dq {eq:.2e}, ddelta {ed:.2e}; mixed Euler {em_q:.2e}")
     assert eq <= 1e-4 and ed <= 1e-4 and abs(em_q) <= 1e-5
+
+
+def test_config5_mixed_gradient_euler(mp, ctx):
+    """lmax = 4000 stress workload, mixed forward + adjoint with the j_l
+    tables regenerated: L = Sum (Gamma * W)^2 is homogeneous of degree 6 in q
+    and in Delta, so <dL/dq, q> = <dL/dDelta, Delta> = 6 L."""
+    cfg = synth.CONFIGS[5]
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    G = pr.gamma("mixed")
+    L = float(((G * W) ** 2).sum())
+    dq, dd = pr.gamma_backward(2 * G * W * W, "mixed")
+    e_q = float((dq * pr.qk).sum()) / (6 * L) - 1
+    e_d = float((dd * pr.delta).sum()) / (6 * L) - 1
+    print(f"lmax=4000 mixed Euler identities: {e_q:.2e}, {e_d:.2e}")
+    assert np.all(np.isfinite(_np(dq))) and np.all(np.isfinite(_np(dd)))
+    assert abs(e_q) <= 1e-4 and abs(e_d) <= 1e-4

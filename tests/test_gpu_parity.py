@@ -320,3 +320,53 @@ def test_gamma_mixed_vs_fp64_config2(mp, ctx, oracle):
     rows, cols = np.unravel_index(idx, gm.shape)
     ref = oracle.gamma_entries(inp, rows, cols)
     assert np.abs(gm[rows, cols] - ref).max() <= MIXED_BAR * np.abs(g64).max()
+
+
+# ------------------------------------------------------------------ large workloads
+def _golden_samples(cfg):
+    """(rows, cols, values) stored by tests/golden/make_oracle_samples.py
+    (oracle values of seeded Gamma entries; computing them takes the oracle
+    minutes)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"oracle_gamma_{cfg.name}.txt")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle samples for {cfg.name}")
+    a = np.loadtxt(path, comments="#", ndmin=2)
+    return a[:, 0].astype(np.int64), a[:, 1].astype(np.int64), a[:, 2]
+
+
+def test_gamma_config3_sampled(mp, ctx):
+    """lmax = 2500, 4960 x 4960 symmetric Gamma: both paths against stored
+    oracle entries, and the mixed path against the FP64 path."""
+    cfg = synth.CONFIGS[3]
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    g64 = _np(pr.gamma("fp64"))
+    gm = _np(pr.gamma("mixed"))
+    assert g64.shape == (4960, 4960) and np.all(np.isfinite(g64))
+    rows, cols, ref = _golden_samples(cfg)
+    scale = np.abs(g64).max()
+    e64 = np.abs(g64[rows, cols] - ref).max() / scale
+    em = np.abs(gm[rows, cols] - ref).max() / scale
+    ew = normwise(gm, g64)
+    print(f"lmax=2500: FP64 vs oracle {e64:.2e}, mixed vs oracle {em:.2e}, mixed vs FP64 {ew:.2e}")
+    assert e64 <= FP64_BAR and em <= MIXED_BAR and ew <= MIXED_BAR
+
+
+@pytest.fixture(scope="module")
+def config5(mp, ctx):
+    cfg = synth.CONFIGS[5]
+    inp = synth.make_inputs(cfg)
+    return cfg, inp, mp.projection_from_inputs(ctx, inp)
+
+
+def test_gamma_config5_mixed_sampled(mp, ctx, config5):
+    """lmax = 4000, 11480 x 11480 symmetric Gamma (the stress workload),
+    mixed path against stored oracle entries."""
+    cfg, inp, pr = config5
+    gm = _np(pr.gamma("mixed"))
+    assert gm.shape == (11480, 11480) and np.all(np.isfinite(gm))
+    rows, cols, ref = _golden_samples(cfg)
+    em = np.abs(gm[rows, cols] - ref).max() / np.abs(gm).max()
+    print(f"lmax=4000: mixed vs oracle {em:.2e}")
+    assert em <= MIXED_BAR
