@@ -887,8 +887,8 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         double *bhat = (double *)ws_get(c, W_BHAT, sizeof(double) * (size_t)d.np * d.L * d.nr);
         {
             StageTimer tm(c, MODAL_STAGE_ADJ_S);
-            hipck(c, launch_betahat(d.na, d.np, d.nr, d.ldmu, d.L, upad, f.wl, f.ql, f.P, Shat, f.wz, bhat,
-                                    c->stream),
+            hipck(c, launch_betahat(d.na, d.np, d.nr, d.nmu, d.ldmu, d.L, g->lmin, upad, f.wl, f.ql, f.P, Shat,
+                                    f.wz, bhat, c->stream),
                   "dL/dbeta");
         }
         // (b) adjoint: j_l regenerated in l chunks
@@ -903,7 +903,9 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
             st.e = (int *)(st.c + nitems);
             st.efin = st.e + nitems;
             const size_t per_l = (size_t)nitems * sizeof(double);
-            int cl = (int)std::max<size_t>(1, std::min<size_t>((size_t)d.L, ((size_t)512 << 20) / per_l));
+            // l chunks of at most 512 MB of j_l values and 4096 l (grid limits)
+            int cl = (int)std::max<size_t>(1, std::min<size_t>({(size_t)d.L, ((size_t)512 << 20) / per_l,
+                                                                (size_t)4096}));
             double *jd = (double *)ws_get(c, W_JCHUNK, per_l * cl);
             double *ah = (double *)ws_get(c, W_AHAT, sizeof(double) * (size_t)cl * d.np * d.nk);
             hipck(c, launch_bessel_prepare(nitems, nullptr, f.G.k, d.nk, f.G.r, g->lmax, st, c->stream),

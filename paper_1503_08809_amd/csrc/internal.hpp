@@ -55,16 +55,11 @@ hipError_t launch_beta_gemm(int nl, int l0, int lmin, int L, int nk, int nr, int
                             const double *qk, double *beta, hipStream_t s);
 
 // Step c: S rows.  Row u = a * np + p holds, for each r, ldmu values (zero
-// past nmu).  upad == 0: caller layout S[u][r][ldmu], unscaled.  upad > 0:
+// past nmu), computed with the mu parity of P_l at nodes symmetric about 0
+// (half the work of the plain product); ldP is the row length of P (nodes
+// ascending).  upad == 0: caller layout S[u][r][ldmu], unscaled.  upad > 0:
 // scaled by wz[z] (the cube root of the quadrature weight) and z-blocked,
 // St[z / 32][u][z % 32] with z = r * ldmu + mu and upad rows per block.
-hipError_t launch_s_gemm(int na, int np, int nr, int nmu, int ldmu, int L,
-                         const double *wl, const double *ql, const double *beta,
-                         const double *P, int ldP, const double *wz, int64_t upad, double *S,
-                         hipStream_t s);
-// The same product using the mu parity of P_l at nodes symmetric about 0
-// (half the work); ldP is the row length of P (nodes ascending).  Same output
-// conventions as launch_s_gemm.
 hipError_t launch_s_parity(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, const double *wl,
                           const double *ql, const double *beta, const double *P, int ldP, const double *wz,
                           int64_t upad, double *S, hipStream_t s);
@@ -161,9 +156,9 @@ hipError_t launch_adj_triple_f64(const int2 *pblocks, int npb, int U, int64_t up
 // S32[i] = St[i] for i < n, 0 for n <= i < ntot
 hipError_t launch_f32_copy(int64_t n, int64_t ntot, const double *St, float *S32, hipStream_t s);
 // dL/dbeta from dL/dSt (z-blocked, times wz on read)
-hipError_t launch_betahat(int na, int np, int nr, int ldmu, int L, int64_t upad, const double *wl,
-                          const double *ql, const double *P, const double *Shat, const double *wz, double *bhat,
-                          hipStream_t s);
+hipError_t launch_betahat(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, int64_t upad,
+                          const double *wl, const double *ql, const double *P, const double *Shat,
+                          const double *wz, double *bhat, hipStream_t s);
 hipError_t launch_ahat(int nl, int l0, int lmin, int L, int np, int nk, int nr, const double *bhat,
                        const double *J, double *Ahat, hipStream_t s);
 hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const double *k, const double *wk,

@@ -12,7 +12,8 @@
 // block kernels (k_adjoint_f64.hip, k_adjoint_mx.hip) as
 // Hc[u][(v,w)] = 3 c_vw H[u,v,w] over pairs v <= w, and dL/dS = W^(1/3) dL/dSt.
 // Step c.  betahat_p(l, r) = Sum_{a, mu} [w_l qbar_a(l) P_l(mu)] Shat_ap(r, mu):
-//   one GEMM per p with the (a, mu) depth and a generated A operand.
+//   per p and per parity of l, one GEMM with the (a, mu >= 0) depth, a
+//   generated A operand and the mu-symmetrised dL/dS as B operand.
 // Step b.  Ahat_l[p, k] = Sum_r betahat_p(l, r) j_l(k r) per l on regenerated
 //   j_l chunks; then dq_p(k) = Sum_l c_k Delta_l(k) Ahat_l[p, k] and
 //   dDelta_l(k) = c_k Sum_p q_p(k) Ahat_l[p, k], c_k = (2/pi) wk k^2, with the
@@ -146,27 +147,55 @@ __global__ void k_build_hc_f64(int kind, int U, int np, int na, const int *__res
 }
 
 // ---- betahat ------------------------------------------------------------------
-struct BetaHatOp {
-    static constexpr bool a_k_fast = true;    // (a, mu) with mu contiguous
-    static constexpr bool b_k_fast = true;    // Shat z-blocked: mu contiguous within 32
-    int M, N, K;                              // L, nr, na * ldmu
-    int np, ldmu, nl;
+// The same contraction using the mu parity of P_l at nodes symmetric about
+// 0: Sum_mu P_l(mu) X(mu) = Sum_{mu >= 0} P_l(mu) [X(mu) + (-1)^l X(-mu)]
+// (the node mu = 0, if any, counted once), so the rows l of one parity are
+// one product over (a, mu >= 0): half the work.  Rows li0, li0 + 2, ...
+// n / d for 0 <= n < 2^31 and 1 <= d < 10^6 without an integer division:
+// n / d is formed in FP64 with absolute error below 2^-22, and the offset
+// 2^-20 < 1 / d lifts exact quotients clear of it without reaching the next
+// integer.
+struct DivBy {
+    int d;
+    double inv;
+    __device__ int quot(int n) const { return (int)((double)n * inv + 0x1p-20); }
+};
+
+struct BetaHatParOp {
+    static constexpr bool a_k_fast = true;    // (a, mu >= 0) with mu contiguous
+    static constexpr bool b_k_fast = true;
+    int M, N, K;                              // rows of this parity, nr, na * nh
+    int np, ldmu, nh, ioff, L, li0;
+    DivBy bynh;                               // kk -> (a, mu index)
+    double sgn;                               // (-1)^l of these rows
     int64_t upad;
     const double *wl, *ql, *P, *Shat, *wz;
     double *bhat;
-    __device__ double a(int, int l, int kk) const
+    struct RawA { double w, q, p; };
+    struct RawB { double wp, sp, wm, sm, cp, cm; };
+    __device__ RawA fa(int, int m, int kk) const
     {
-        const int ia = kk / ldmu, mu = kk % ldmu;
-        return wl[l] * ql[(size_t)ia * nl + l] * P[(size_t)l * ldmu + mu];
+        const int ia = bynh.quot(kk), jj = kk - ia * nh, li = li0 + 2 * m;
+        return RawA{wl[li], ql[(size_t)ia * L + li], P[(size_t)li * ldmu + ioff + jj]};
     }
-    // dL/dS = W^(1/3) dL/dSt
-    __device__ double bv(int p, int kk, int r) const
+    __device__ double ma(const RawA &v) const { return v.w * v.q * v.p; }
+    // X(+mu) + sgn X(-mu), X = W^(1/3) dL/dSt at node ioff + jj and its mirror;
+    // at the node mu = 0 (its own mirror) X counts once, and only for even l
+    __device__ RawB fb(int p, int kk, int r) const
     {
-        const int ia = kk / ldmu, mu = kk % ldmu;
-        const int64_t z = (int64_t)r * ldmu + mu;
-        return wz[z] * Shat[(((size_t)(z >> 5) * upad + ia * np + p) << 5) + (z & 31)];
+        const int ia = bynh.quot(kk), jj = kk - ia * nh;
+        const size_t u = (size_t)ia * np + p;
+        const int64_t zp = (int64_t)r * ldmu + ioff + jj, zm = (int64_t)r * ldmu + nh - 1 - jj;
+        const bool centre = zp == zm;
+        return RawB{wz[zp], Shat[(((size_t)(zp >> 5) * upad + u) << 5) + (zp & 31)],
+                    wz[zm], Shat[(((size_t)(zm >> 5) * upad + u) << 5) + (zm & 31)],
+                    centre && sgn < 0.0 ? 0.0 : 1.0, centre ? 0.0 : sgn};
     }
-    __device__ void store(int p, int l, int r, double v) const { bhat[((size_t)p * M + l) * N + r] = v; }
+    __device__ double mb(const RawB &v) const { return v.cp * v.wp * v.sp + v.cm * v.wm * v.sm; }
+    __device__ void store(int p, int m, int r, double v) const
+    {
+        bhat[((size_t)p * L + li0 + 2 * m) * N + r] = v;
+    }
 };
 
 // ---- Ahat per l chunk -------------------------------------------------------------
@@ -177,35 +206,41 @@ struct AhatOp {
     int l0, lmin, L;
     const double *bhat, *J;
     double *Ahat;                             // [l - l0][p][k]
-    __device__ double a(int b, int p, int r) const
-    {
-        return bhat[((size_t)p * L + (l0 + b - lmin)) * K + r];
-    }
-    __device__ double bv(int b, int r, int k) const { return J[((size_t)b * K + r) * N + k]; }
+    using RawA = double;
+    using RawB = double;
+    __device__ RawA fa(int b, int p, int r) const { return bhat[((size_t)p * L + (l0 + b - lmin)) * K + r]; }
+    __device__ double ma(RawA v) const { return v; }
+    __device__ RawB fb(int b, int r, int k) const { return J[((size_t)b * K + r) * N + k]; }
+    __device__ double mb(RawB v) const { return v; }
     __device__ void store(int b, int p, int k, double v) const { Ahat[((size_t)b * M + p) * N + k] = v; }
 };
 
+// One thread per (row, k): rows 0..np-1 accumulate dq_p(k) over the chunk's
+// l values (in a fixed order, added to the running sum of earlier chunks),
+// rows np..np+nl-1 write dDelta_l(k) for the chunk's l values.
 __global__ void k_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const double *__restrict__ k,
                             const double *__restrict__ wk, const double *__restrict__ qk,
                             const double *__restrict__ delta, const double *__restrict__ Ahat,
                             double *__restrict__ dq, double *__restrict__ dd, int first)
 {
-    // one thread per k: the chunk's l values in order (deterministic)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
     if (i >= nk) return;
     const double ck = (2.0 / kPi) * wk[i] * k[i] * k[i];
-    for (int p = 0; p < np; ++p) {
+    if (row < np) {
+        if (!dq) return;
+        const int p = row;
         double acc = 0.0;
         for (int b = nl - 1; b >= 0; --b)
             acc += delta[(size_t)(l0 + b - lmin) * nk + i] * Ahat[((size_t)b * np + p) * nk + i];
-        if (dq) dq[(size_t)p * nk + i] = (first ? 0.0 : dq[(size_t)p * nk + i]) + ck * acc;
+        dq[(size_t)p * nk + i] = (first ? 0.0 : dq[(size_t)p * nk + i]) + ck * acc;
+    } else {
+        if (!dd) return;
+        const int b = row - np;
+        double acc = 0.0;
+        for (int p = 0; p < np; ++p) acc += qk[(size_t)p * nk + i] * Ahat[((size_t)b * np + p) * nk + i];
+        dd[(size_t)(l0 + b - lmin) * nk + i] = ck * acc;
     }
-    if (dd)
-        for (int b = 0; b < nl; ++b) {
-            double acc = 0.0;
-            for (int p = 0; p < np; ++p) acc += qk[(size_t)p * nk + i] * Ahat[((size_t)b * np + p) * nk + i];
-            dd[(size_t)(l0 + b - lmin) * nk + i] = ck * acc;
-        }
 }
 
 }  // namespace
@@ -234,12 +269,22 @@ hipError_t launch_build_hc_f64(int kind, int U, int np, int na, const int *inv_a
     return hipGetLastError();
 }
 
-hipError_t launch_betahat(int na, int np, int nr, int ldmu, int L, int64_t upad, const double *wl,
-                          const double *ql, const double *P, const double *Shat, const double *wz, double *bhat,
-                          hipStream_t s)
+hipError_t launch_betahat(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, int64_t upad,
+                          const double *wl, const double *ql, const double *P, const double *Shat,
+                          const double *wz, double *bhat, hipStream_t s)
 {
-    BetaHatOp op{L, nr, na * ldmu, np, ldmu, L, upad, wl, ql, P, Shat, wz, bhat};
-    return run(op, np, s);
+    // rows of each parity of l: li with (lmin + li) even, then odd
+    const int nh = (nmu + 1) / 2, ioff = nmu - nh;
+    for (int par = 0; par < 2; ++par) {
+        const int li0 = (par - lmin) & 1;
+        const int rows = L > li0 ? (L - li0 + 1) / 2 : 0;
+        if (rows == 0) continue;
+        BetaHatParOp op{rows, nr, na * nh, np, ldmu, nh, ioff, L, li0, DivBy{nh, 1.0 / nh}, par ? -1.0 : 1.0,
+                        upad, wl, ql, P, Shat, wz, bhat};
+        const hipError_t e = run(op, np, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_ahat(int nl, int l0, int lmin, int L, int np, int nk, int nr, const double *bhat,
@@ -253,8 +298,9 @@ hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const doub
                             const double *qk, const double *delta, const double *Ahat, double *dq,
                             double *dd, int first, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dq_ddelta, dim3((nk + 127) / 128), dim3(128), 0, s, nl, l0, lmin, np, nk, k, wk, qk,
-                       delta, Ahat, dq, dd, first);
+    if (np + nl > 65535) return hipErrorInvalidValue;       // grid y limit
+    hipLaunchKernelGGL(k_dq_ddelta, dim3((nk + 127) / 128, np + nl), dim3(128), 0, s, nl, l0, lmin, np, nk, k,
+                       wk, qk, delta, Ahat, dq, dd, first);
     return hipGetLastError();
 }
 

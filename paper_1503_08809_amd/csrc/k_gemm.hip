@@ -33,43 +33,15 @@ struct BetaOp {
     int l0, lmin, L;
     const double *Jd, *k, *wk, *qk;
     double *beta;
-    __device__ double a(int b, int m, int kk) const { return Jd[((size_t)b * M + m) * K + kk]; }
-    __device__ double bv(int, int kk, int n) const
-    {
-        const double kv = k[kk];
-        return (2.0 / kPi) * wk[kk] * kv * kv * qk[(size_t)n * K + kk];
-    }
+    using RawA = double;
+    struct RawB { double k, wk, q; };
+    __device__ RawA fa(int b, int m, int kk) const { return Jd[((size_t)b * M + m) * K + kk]; }
+    __device__ double ma(RawA v) const { return v; }
+    __device__ RawB fb(int, int kk, int n) const { return RawB{k[kk], wk[kk], qk[(size_t)n * K + kk]}; }
+    __device__ double mb(const RawB &v) const { return (2.0 / kPi) * v.wk * v.k * v.k * v.q; }
     __device__ void store(int b, int m, int n, double v) const
     {
         beta[((size_t)n * L + (l0 + b - lmin)) * M + m] = v;
-    }
-};
-
-// ---- step c ----------------------------------------------------------------
-struct SOp {
-    static constexpr bool a_k_fast = false;   // beta[p][l][r]: r contiguous
-    static constexpr bool b_k_fast = false;   // P[l][mu]: mu contiguous
-    int M, N, K;                              // nr, ldmu, L
-    int np, nmu, ldP;
-    const double *wl, *ql, *beta, *P, *wz;
-    double *S;
-    int64_t upad;                             // > 0: z-blocked output (see below)
-    __device__ double a(int u, int m, int l) const
-    {
-        const int ia = u / np, ip = u % np;
-        return wl[l] * ql[(size_t)ia * K + l] * beta[((size_t)ip * K + l) * M + m];
-    }
-    __device__ double bv(int, int l, int n) const { return P[(size_t)l * ldP + n]; }
-    __device__ void store(int u, int m, int n, double v) const
-    {
-        if (upad > 0) {
-            // z-blocked rows: St[z / 32][u][z % 32], z = r * ldmu + mu
-            const int64_t z = (int64_t)m * N + n;
-            const size_t o = (((size_t)(z >> 5) * upad + u) << 5) + (z & 31);
-            S[o] = (n < nmu) ? v * wz[z] : 0.0;
-            return;
-        }
-        S[((size_t)u * M + m) * N + n] = (n < nmu) ? v : 0.0;
     }
 };
 
@@ -261,15 +233,6 @@ hipError_t launch_beta_gemm(int nl, int l0, int lmin, int L, int nk, int nr, int
 {
     BetaOp op{nr, np, nk, l0, lmin, L, Jd, k, wk, qk, beta};
     return run(op, nl, s);
-}
-
-hipError_t launch_s_gemm(int na, int np, int nr, int nmu, int ldmu, int L, const double *wl,
-                         const double *ql, const double *beta, const double *P, int ldP,
-                         const double *wz, int64_t upad, double *S, hipStream_t s)
-{
-    if (upad > 0 && (!wz || ldmu % 32 != 0)) return hipErrorInvalidValue;
-    SOp op{nr, ldmu, L, np, nmu, ldP, wl, ql, beta, P, wz, S, upad};
-    return run(op, na * np, s);
 }
 
 hipError_t launch_s_parity(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, const double *wl,

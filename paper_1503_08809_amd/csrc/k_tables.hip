@@ -118,10 +118,12 @@ __global__ void k_gauss_legendre(int n, double *__restrict__ x, double *__restri
     dd z{(1.0 - 1.0 / (8.0 * dn * dn) + 1.0 / (8.0 * dn * dn * dn)) * cos(th), 0.0};
     const bool centre = (n % 2 == 1 && i == half - 1);
     if (centre) z = {0.0, 0.0};
-    // FP64 Newton to a double-precision root, then two double-double steps
-    // (quadratic convergence takes the ~1e-16 error below 1e-30)
-    double zf = z.hi;
-    for (int it = 0; it < 64 && !centre; ++it) {
+    // FP64 Newton to ~1e-13 relative, then two double-double steps (quadratic
+    // convergence: ~1e-26, then far below FP64 resolution).  The FP64 steps
+    // stop at 1e-13: near a root the FP64 value of P_n carries ~n ulp of
+    // rounding noise, so asking for more only repeats steps of noise.
+    double zf = z.hi, dzprev = 1.0;
+    for (int it = 0; it < 16 && !centre; ++it) {
         double p0 = 1.0, p1 = zf;
         for (int l = 1; l < n; ++l) {
             const double p2 = ((2.0 * l + 1.0) * zf * p1 - (double)l * p0) / (double)(l + 1);
@@ -131,7 +133,8 @@ __global__ void k_gauss_legendre(int n, double *__restrict__ x, double *__restri
         const double dpf = dn * (zf * p1 - p0) / ((zf - 1.0) * (zf + 1.0));
         const double dz = p1 / dpf;
         zf -= dz;
-        if (fabs(dz) <= 2e-16 * fabs(zf) + 1e-300) break;
+        if (fabs(dz) <= 1e-13 * fabs(zf) + 1e-300 || fabs(dz) >= dzprev) break;
+        dzprev = fabs(dz);
     }
     z = {zf, 0.0};
     dd pn, pn1, dp{1.0, 0.0};
