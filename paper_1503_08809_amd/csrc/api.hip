@@ -847,7 +847,7 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         hipck(c, hipMemcpyAsync(dinvp, invp.data(), sizeof(int) * invp.size(), hipMemcpyHostToDevice, c->stream),
               "H2D");
         // pair blocks (v block <= w block) of 16 rows
-        const int nvb = (d.U + 15) / 16, nib = (int)(upad / adj_rowblock());
+        const int nvb = (d.U + 15) / 16;
         std::vector<int2> pbl;
         for (int vb = 0; vb < nvb; ++vb)
             for (int wb = vb; wb < nvb; ++wb) pbl.push_back(make_int2(vb, wb));
@@ -859,7 +859,8 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         const int64_t nzb = ldz / 32, nzbp = (nzb + kZBlockPad - 1) / kZBlockPad * kZBlockPad;
         double *Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)nzbp * upad * 32);
         if (prec == MODAL_MIXED) {
-            uint4 *Hc = (uint4 *)ws_get(c, W_H, sizeof(uint4) * (size_t)npb * nib * 8192);
+            const int nib = (int)(upad / adj_rowblock_mixed());
+            uint4 *Hc = (uint4 *)ws_get(c, W_H, sizeof(uint4) * (size_t)npb * nib * 16384);
             float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * (size_t)nzbp * upad * 32);
             {
                 StageTimer tm(c, MODAL_STAGE_ADJ_PREP);
@@ -873,6 +874,7 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
             hipck(c, launch_adj_triple_mixed(dpb, npb, d.U, upad, nzbp, s32, Hc, Shat, c->stream), "dL/dS");
         } else {
+            const int nib = (int)(upad / adj_rowblock());
             double *Hc = (double *)ws_get(c, W_H, sizeof(double) * (size_t)npb * nib * 32768);
             {
                 StageTimer tm(c, MODAL_STAGE_ADJ_PREP);

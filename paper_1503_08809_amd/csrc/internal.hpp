@@ -142,7 +142,8 @@ hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *
 // in each kernel's operand order.  Shat and St/S32 are z-blocked with nzb z
 // blocks (a multiple of kZBlockPad, zero past the data); rows >= U of Shat
 // are left unwritten.
-int adj_rowblock();
+int adj_rowblock();            // FP64 kernel (Hc: 32768 doubles per pair block and row block)
+int adj_rowblock_mixed();      // mixed kernel (Hc: 16384 uint4 per pair block and row block)
 hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
                                  const double *G, int tp, const int2 *pblocks, int npb, int nib, uint4 *Hc,
                                  hipStream_t s);

@@ -78,7 +78,7 @@ __device__ double adj_h(int kind, int np, int na, const int *__restrict__ inv_a,
 
 // Hc[u][(v,w)] = 3 c_vw H[u,v,w] (c = 2 for v < w, 1 for v = w, 0 for v > w)
 // split into BF16 hi and lo, in the A-operand order of the mixed adjoint
-// kernel: Hc[pair block][row block of 128][step][row tile][hi/lo][lane], a
+// kernel: Hc[pair block][row block of 256][step][row tile][hi/lo][lane], a
 // lane holding rows 16-tile + lane % 16 and step pairs 8 (lane / 16) .. + 7.
 __device__ __forceinline__ uint32_t bf16_bits(float f)
 {
@@ -90,14 +90,14 @@ __global__ void k_build_hc_mx(int kind, int U, int np, int na, const int *__rest
                               const int *__restrict__ inv_p, const double *__restrict__ G, int tp,
                               const int2 *__restrict__ pblocks, int npb, int nib, uint4 *__restrict__ Hc)
 {
-    const int64_t n = (int64_t)npb * nib * 8 * 8 * 64;
+    const int64_t n = (int64_t)npb * nib * 8 * 16 * 64;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int lane = (int)(e & 63), rt = (int)((e >> 6) & 7), ks = (int)((e >> 9) & 7);
-        const int64_t pbib = e >> 12;
+        const int lane = (int)(e & 63), rt = (int)((e >> 6) & 15), ks = (int)((e >> 10) & 7);
+        const int64_t pbib = e >> 13;
         const int ib = (int)(pbib % nib), pb = (int)(pbib / nib);
         const int2 b = pblocks[pb];
-        const int u = ib * 128 + rt * 16 + (lane & 15);
+        const int u = ib * 256 + rt * 16 + (lane & 15);
         float x[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -249,7 +249,7 @@ hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv
                                  const double *G, int tp, const int2 *pblocks, int npb, int nib, uint4 *Hc,
                                  hipStream_t s)
 {
-    const int64_t n = (int64_t)npb * nib * 8 * 8 * 64;
+    const int64_t n = (int64_t)npb * nib * 8 * 16 * 64;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_build_hc_mx, dim3((unsigned)blocks), dim3(256), 0, s, kind, U, np, na, inv_a, inv_p,

@@ -35,10 +35,12 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
-constexpr int AI = 128;            // output rows per workgroup
+constexpr int AI = 256;            // output rows per workgroup
+constexpr int RB = 4;              // 16-row tiles per wave
+constexpr int TW = 4;              // 16-wide column tiles per wave
 constexpr int PB = 16;             // pair block: 16 v x 16 w
 constexpr int KS = PB * PB / 32;   // 32-pair steps per pair block
-constexpr int ZT = 256;            // z values per workgroup
+constexpr int ZT = 128;            // z values per workgroup
 constexpr int NCT = ZT / 16;       // 16-wide column tiles
 constexpr int ZBW = ZT / 32;       // z blocks of 32 per workgroup
 constexpr int kFlush = 32;         // pair blocks per FP32 partial sum
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int rg = wave & 3, ch = wave >> 2;   // 32-row group, 8-tile column half
+    const int rg = wave & 3, ch = wave >> 2;   // 64-row group, 4-tile column half
     // tasks (row block, z tile), row block outer, dealt to the 8 XCDs in
     // contiguous runs
     const int ntasks = A.nib * A.nzt;
@@ -98,53 +100,50 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
     }();
     const int ib = task / A.nzt, zt = task % A.nzt;
     const int64_t zb0 = (int64_t)zt * ZBW;
-    const int u0 = ib * AI + rg * 32;
+    const int u0 = ib * AI + rg * 16 * RB;
     const bool active = u0 < A.U;              // wave-uniform: some row holds data
 
-    f4 acc[2][8];
+    f4 acc[RB][TW];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // ---- staging of a pair block's 32 source rows over the z tile: 2048
-    // float4, four per thread.  v rows (i = 0, 1): a wave covers one row's
-    // 256 z (contiguous LDS writes); w rows (i = 2, 3): consecutive lanes take
-    // consecutive rows, so the transposed LDS writes spread over the banks.
-    // part i (0..3) of pair block pb: one float4 per thread
+    // ---- staging of a pair block's 32 source rows over the z tile: 1024
+    // float4, two per thread.  Part 0, the v rows: a wave covers two rows'
+    // 128 z (contiguous LDS writes); part 1, the w rows: consecutive lanes
+    // take consecutive rows, so the transposed LDS writes spread over banks.
     auto sload1 = [&](int pb, int i) -> f4 {
         const int2 b = A.pblocks[pb];
-        const int f = t + 512 * (i & 1);
         int grow, z4;
-        if (i < 2) { grow = b.x * PB + (f >> 6); z4 = f & 63; }
-        else       { grow = b.y * PB + (f & 15); z4 = f >> 4; }
+        if (i == 0) { grow = b.x * PB + (t >> 5); z4 = t & 31; }
+        else        { grow = b.y * PB + (t & 15); z4 = t >> 4; }
         return *reinterpret_cast<const f4 *>(S32 + (((zb0 + (z4 >> 3)) * A.upad + grow) << 5) + 4 * (z4 & 7));
     };
     auto sstore1 = [&](int sb, int i, f4 v) {
-        const int f = t + 512 * (i & 1);
-        if (i < 2) {
-            *reinterpret_cast<f4 *>(&SrcJ[sb][f >> 6][4 * (f & 63)]) = v;
+        if (i == 0) {
+            *reinterpret_cast<f4 *>(&SrcJ[sb][t >> 5][4 * (t & 31)]) = v;
         } else {
-            const int zl = 4 * (f >> 4), row = f & 15;
+            const int zl = 4 * (t >> 4), row = t & 15;
 #pragma unroll
             for (int e = 0; e < 4; ++e) SrcK[sb][zl + e][row] = v[e];
         }
     };
     // ---- operand of step ks of the pair block staged in SrcJ/K[sb]: column
-    // tiles 2 wave, 2 wave + 1.  Lane: z = tile * 16 + lane % 16, v local =
-    // 2 ks + lane / 32, w local = 8 ((lane / 16) % 2) + e (matrix-core depth
-    // index 8 (lane / 16) + e of the step).  The LDS reads are issued early
-    // (gread) and the products formed later (gwrite), under matrix-core work.
+    // tile `wave`.  Lane: z = tile * 16 + lane % 16, v local = 2 ks + lane /
+    // 32, w local = 8 ((lane / 16) % 2) + e (matrix-core depth index
+    // 8 (lane / 16) + e of the step).  The LDS reads are issued early (gread)
+    // and the products formed later (gwrite), under matrix-core work.
     float gsv;
     f4 gw0, gw1;
-    auto gread = [&](int sb, int ks, int q) {
+    auto gread = [&](int sb, int ks) {
         const int vl = 2 * ks + (lane >> 5), wh = ((lane >> 4) & 1) * 8;
-        const int zl = (2 * wave + q) * 16 + (lane & 15);
+        const int zl = wave * 16 + (lane & 15);
         gsv = SrcJ[sb][vl][zl];
         gw0 = *reinterpret_cast<const f4 *>(&SrcK[sb][zl][wh]);
         gw1 = *reinterpret_cast<const f4 *>(&SrcK[sb][zl][wh + 4]);
     };
-    auto gwrite = [&](int q, int bb) {
+    auto gwrite = [&](int bb) {
         float v[8];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -154,39 +153,38 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
         uint32_t h[4], l[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], h[e], l[e]);
-        const int ct = 2 * wave + q;
-        Bb[bb][ct][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
-        Bb[bb][ct][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
+        Bb[bb][wave][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
+        Bb[bb][wave][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
     };
-    // ---- A fragments (Hc) of step (pb, ks) for this wave's two row tiles:
-    // Hc[pb][ib][ks][row tile][hi/lo][lane]; loaded one step ahead
-    uint4 ah[2], al[2], nah[2], nal[2];
-    auto aload = [&](int pb, int ks, uint4 (&h)[2], uint4 (&l)[2]) {
-        const uint4 *p = Hc + ((((size_t)pb * A.nib + ib) * KS + ks) * 8 + 2 * rg) * 128 + lane;
+    // ---- A fragments (Hc) of step (pb, ks) for this wave's row tiles:
+    // Hc[pb][ib][ks][row tile][hi/lo][lane]
+    uint4 ah[RB], al[RB];
+    auto aload = [&](int pb, int ks) {
+        const uint4 *p = Hc + ((((size_t)pb * A.nib + ib) * KS + ks) * (AI / 16) + RB * rg) * 128 + lane;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            h[i] = p[i * 128];
-            l[i] = p[i * 128 + 64];
+        for (int i = 0; i < RB; ++i) {
+            ah[i] = p[i * 128];
+            al[i] = p[i * 128 + 64];
         }
     };
 
-    // ---- output: this wave's tiles (row tile i, column tile 8 ch + j) at
-    // Shat[zb][u][32], u = u0 + 16 i + 4 (lane / 16) + q, z = 16 (8 ch + j) + lane % 16
-    const int zl0 = ch * 128 + (lane & 15);
+    // ---- output: this wave's tiles (row tile i, column tile TW ch + j) at
+    // Shat[zb][u][32], u = u0 + 16 i + 4 (lane / 16) + q, z = 16 (TW ch + j) + lane % 16
+    const int zl0 = ch * 16 * TW + (lane & 15);
     auto flush = [&](bool first) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < RB; ++i) {
             const int ub = u0 + 16 * i + 4 * (lane >> 4);
-            double old[8][4];
+            double old[TW][4];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < TW; ++j) {
                 const int zl = zl0 + 16 * j;
                 const double *p = Shat + ((((zb0 + (zl >> 5)) * A.upad + ub) << 5) + (zl & 31));
 #pragma unroll
                 for (int q = 0; q < 4; ++q) old[j][q] = first ? 0.0 : p[q * 32];
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < TW; ++j) {
                 const int zl = zl0 + 16 * j;
                 double *p = Shat + ((((zb0 + (zl >> 5)) * A.upad + ub) << 5) + (zl & 31));
 #pragma unroll
@@ -194,27 +192,22 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
             }
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < RB; ++i)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < TW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     };
 
     const int npb = A.npb;
-    // prologue: sources of pair block 0, operand of step (0, 0), A of (0, 0),
-    // and the loads of pair block 1's sources
+    // prologue: sources of pair block 0, operand of step (0, 0), A of (0, 0)
     {
-        f4 v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = sload1(0, i);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sstore1(0, i, v[i]);
+        const f4 v0 = sload1(0, 0), v1 = sload1(0, 1);
+        sstore1(0, 0, v0);
+        sstore1(0, 1, v1);
     }
     lds_barrier();
-    gread(0, 0, 0);
-    gwrite(0, 0);
-    gread(0, 0, 1);
-    gwrite(1, 0);
-    aload(0, 0, ah, al);
+    gread(0, 0);
+    gwrite(0);
+    aload(0, 0);
     lds_barrier();
     f4 sreg = f4{0.f, 0.f, 0.f, 0.f};
 
@@ -229,62 +222,52 @@ __global__ __launch_bounds__(512) void k_adj_bt(AdjArgs A, const float *__restri
             const bool last_step = ks == KS - 1;
             const int nsb = last_step ? sb ^ 1 : sb, nks = last_step ? 0 : ks + 1;
             const bool has_next = !(last_step && pb + 1 == npb);
-            // A fragments of the next step, a whole step ahead of their use
-            if (has_next) aload(last_step ? pb + 1 : pb, nks, nah, nal);
+            if (has_next) gread(nsb, nks);
             if (active) {
-                // B fragments two tiles ahead of their matrix-core use
-                uint4 bh[3], bl[3];
+                // B fragments one tile ahead of their matrix-core use
+                uint4 bh = Bb[bb][ch * TW][0][lane], bl = Bb[bb][ch * TW][1][lane];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    bh[j] = Bb[bb][ch * 8 + j][0][lane];
-                    bl[j] = Bb[bb][ch * 8 + j][1][lane];
-                }
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (j + 2 < 8) {
-                        bh[(j + 2) % 3] = Bb[bb][ch * 8 + j + 2][0][lane];
-                        bl[(j + 2) % 3] = Bb[bb][ch * 8 + j + 2][1][lane];
+                for (int j = 0; j < TW; ++j) {
+                    uint4 nbh = bh, nbl = bl;
+                    if (j + 1 < TW) {
+                        nbh = Bb[bb][ch * TW + j + 1][0][lane];
+                        nbl = Bb[bb][ch * TW + j + 1][1][lane];
                     }
-                    // operand of the next step, one tile at a time: LDS reads
-                    // three matrix-core groups before the products
-                    if (has_next && (j == 0 || j == 3)) gread(nsb, nks, j / 3);
-                    const bf8 h8 = as_bf8(bh[j % 3]), l8 = as_bf8(bl[j % 3]);
+                    const bf8 h8 = as_bf8(bh), l8 = as_bf8(bl);
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < RB; ++i)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), h8, acc[i][j], 0, 0, 0);
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < RB; ++i)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), l8, acc[i][j], 0, 0, 0);
 #pragma unroll
-                    for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < RB; ++i)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), h8, acc[i][j], 0, 0, 0);
-                    if (has_next && (j == 2 || j == 5)) gwrite(j / 3, bb ^ 1);
+                    // operand of the next step
+                    if (j == 1 && has_next) gwrite(bb ^ 1);
                     __builtin_amdgcn_sched_barrier(0);
+                    bh = nbh;
+                    bl = nbl;
                 }
             } else if (has_next) {
-                gread(nsb, nks, 0);
-                gwrite(0, bb ^ 1);
-                gread(nsb, nks, 1);
-                gwrite(1, bb ^ 1);
+                gwrite(bb ^ 1);
             }
             // sources of pair block pb + 1 into the other buffer (its last
             // reader formed this block's first operand): one float4 per thread
-            // per step, loaded in steps 0..3 and stored one step later, so they
-            // are visible well before step KS - 1 forms the next block's operand
+            // per step, loaded in steps 0 and 1 and stored one step later, well
+            // before step KS - 1 forms the next block's operand
             if (pb + 1 < npb) {
-                if (ks >= 1 && ks <= 4) sstore1(sb ^ 1, ks - 1, sreg);
-                if (ks <= 3) sreg = sload1(pb + 1, ks);
+                if (ks == 1 || ks == 2) sstore1(sb ^ 1, ks - 1, sreg);
+                if (ks <= 1) sreg = sload1(pb + 1, ks);
             }
             if (last_step && (++since_flush == kFlush || pb + 1 == npb)) {
                 if (active) flush(first);
                 since_flush = 0;
                 first = false;
             }
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                ah[i] = nah[i];
-                al[i] = nal[i];
-            }
+            // A fragments of the next step (the other wave of the SIMD covers
+            // their latency)
+            if (has_next) aload(last_step ? pb + 1 : pb, nks);
             lds_barrier();
         }
     }
@@ -328,5 +311,7 @@ hipError_t launch_f32_copy(int64_t n, int64_t ntot, const double *St, float *S32
 }
 
 static_assert(kZBlockPad % ZBW == 0, "z tiles must divide the z-block padding");
+static_assert(kRowPad % AI == 0, "row blocks must divide the row padding");
+int adj_rowblock_mixed() { return AI; }
 
 }  // namespace mp
