@@ -859,20 +859,17 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         const int64_t nzb = ldz / 32, nzbp = (nzb + kZBlockPad - 1) / kZBlockPad * kZBlockPad;
         double *Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)nzbp * upad * 32);
         if (prec == MODAL_MIXED) {
-            const int nib = (int)(upad / adj_rowblock_mixed());
-            uint4 *Hc = (uint4 *)ws_get(c, W_H, sizeof(uint4) * (size_t)npb * nib * 16384);
-            float *s32 = (float *)ws_get(c, W_S32, sizeof(float) * (size_t)nzbp * upad * 32);
+            const int nib = (int)(upad / adj_fac_rowblock()), nws = (d.U + 31) / 32;
+            uint4 *Hc = (uint4 *)ws_get(c, W_H, sizeof(uint4) * (size_t)v_step_offset(d.U, nws) * nib * 2048);
+            uint4 *sb = (uint4 *)ws_get(c, W_S32, sizeof(uint4) * (size_t)nzbp * nws * 256);
             {
                 StageTimer tm(c, MODAL_STAGE_ADJ_PREP);
-                hipck(c, launch_build_hc_mixed(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib,
-                                               Hc, c->stream),
+                hipck(c, launch_build_hc_fac(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, nib, Hc, c->stream),
                       "build Hc");
-                hipck(c, launch_f32_copy((int64_t)nzbp * upad * 32, (int64_t)nzbp * upad * 32, f.St, s32,
-                                         c->stream),
-                      "FP32 copy of S");
+                hipck(c, launch_split_b(nzbp, d.U, upad, f.St, sb, c->stream), "split S");
             }
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
-            hipck(c, launch_adj_triple_mixed(dpb, npb, d.U, upad, nzbp, s32, Hc, Shat, c->stream), "dL/dS");
+            hipck(c, launch_adj_fac(d.U, upad, nzbp, f.St, sb, Hc, Shat, c->stream), "dL/dS");
         } else {
             const int nib = (int)(upad / adj_rowblock());
             double *Hc = (double *)ws_get(c, W_H, sizeof(double) * (size_t)npb * nib * 32768);

@@ -102,22 +102,17 @@ constexpr int kZBlockPad = 8;
 hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group_rows,
                              TriplePlan &plan, std::string &err);
 void free_triple_plan(TriplePlan &plan);
-// shapes of the two kernels
+// shape of the FP64 kernel
 void triple_f64_shape(int &rowblock, int &tiles_per_group, int &group_rows);
-void triple_mixed_shape(int &rowblock, int &tiles_per_group, int &group_rows);
 
 hipError_t launch_triple_f64(const TriplePlan &plan, int64_t upad, int64_t ldz,
                              const double *St, double *T, hipStream_t s);
-// Mixed: S32 is the FP32 copy of the scaled rows (sources of the generated
-// operand, same z-blocked layout) and SA their BF16 (hi, lo) split packed
-// per 8 z values ([z / 32][Upad][4][8 hi, 8 lo]); each r holds nmu_pad z
-// values (a multiple of 32).
-hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t upad, int64_t ldz, int nr,
-                               int nmu_pad, const float *S32, const uint16_t *SA, double *T,
-                               hipStream_t s);
-// Block-triple plan of the mixed kernel: tasks (ib, jb, kb) of 256 x 16 x 16
+// Block-triple plan of the mixed kernel: tasks (ib, jb, kb) of 128 x 16 x 16
 // rows, the task index of every block triple (-1 if it holds no i <= j <= k),
-// and T packed per task.
+// and T packed per task.  The kernel reads S32, the FP32 copy of the scaled
+// rows (z-blocked like St), and SA, their BF16 (hi, lo) split packed per 8 z
+// values ([z / 32][Upad][4][8 hi, 8 lo]); each r holds nmu_pad z values (a
+// multiple of 32).
 struct BTPlan {
     int U = 0;
     int nib = 0, njb = 0, nkb = 0;
@@ -132,30 +127,38 @@ hipError_t launch_triple_bt(const BTPlan &plan, int64_t upad, int64_t ldz, int n
                             const float *S32, const uint16_t *SA, double *T, hipStream_t s);
 hipError_t launch_gather_bt(int kind, int ta, int tp, const int *tri_a, const int *tri_p, int np,
                             const BTPlan &plan, const double *T, double *gamma, hipStream_t s);
-// Elementwise over the n values (a multiple of 8): FP32 copy and BF16 split.
+// Elementwise over the n values (a multiple of 8): S32 and SA as above.
 hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *SA,
                              hipStream_t s);
 
 // Adjoint stages (k_adjoint*.hip).  Step d: dL/dSt_u(z) = Sum_{v <= w}
-// Hc[u][(v,w)] St_v(z) St_w(z) over pair blocks pblocks[npb] (16-row v block
-// <= w block) and nib row blocks of adj_rowblock() rows; Hc is built from G
-// in each kernel's operand order.  Shat and St/S32 are z-blocked with nzb z
-// blocks (a multiple of kZBlockPad, zero past the data); rows >= U of Shat
-// are left unwritten.
+// Hc[u][(v,w)] St_v(z) St_w(z), Hc built from G in each kernel's operand
+// order.  FP64 (k_adjoint_f64.hip): over pair blocks pblocks[npb] (16-row v
+// block <= w block) and nib row blocks of adj_rowblock() rows.  Shat and St
+// are z-blocked with nzb z blocks (a multiple of kZBlockPad, zero past the
+// data); rows >= U of Shat are left unwritten.
 int adj_rowblock();            // FP64 kernel (Hc: 32768 doubles per pair block and row block)
-int adj_rowblock_mixed();      // mixed kernel (Hc: 16384 uint4 per pair block and row block)
-hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
-                                 const double *G, int tp, const int2 *pblocks, int npb, int nib, uint4 *Hc,
-                                 hipStream_t s);
-hipError_t launch_adj_triple_mixed(const int2 *pblocks, int npb, int U, int64_t upad, int64_t nzb,
-                                   const float *S32, const uint4 *Hc, double *Shat, hipStream_t s);
 hipError_t launch_build_hc_f64(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
                                const double *G, int tp, const int2 *pblocks, int npb, int nib, double *Hc,
                                hipStream_t s);
 hipError_t launch_adj_triple_f64(const int2 *pblocks, int npb, int U, int64_t upad, int64_t nzb,
                                  const double *St, const double *Hc, double *Shat, hipStream_t s);
-// S32[i] = St[i] for i < n, 0 for n <= i < ntot
-hipError_t launch_f32_copy(int64_t n, int64_t ntot, const double *St, float *S32, hipStream_t s);
+// Factored mixed adjoint of step d (k_adjoint_fac.hip): for every v, the w
+// steps (32 wide) from the one holding v to the last; Hc is stored per
+// (v, w step) as [v_step_offset(v) + ws - v / 32][row block of 256][row
+// tile][hi/lo][lane] (uint4, 2048 per step and row block), and St pre-split in
+// the B-operand order (SB, uint4, 128 per z block of 32, w step and half).
+__host__ __device__ inline int64_t v_step_offset(int v, int nws)
+{
+    const int64_t a = v >> 5, b = v & 31;      // Sum_{v' < v} (nws - v' / 32)
+    return 32 * (a * nws - a * (a - 1) / 2) + b * (nws - a);
+}
+int adj_fac_rowblock();
+hipError_t launch_build_hc_fac(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                               const double *G, int tp, int nib, uint4 *Hc, hipStream_t s);
+hipError_t launch_split_b(int64_t nzb, int U, int64_t upad, const double *St, uint4 *SB, hipStream_t s);
+hipError_t launch_adj_fac(int U, int64_t upad, int64_t nzb, const double *St, const uint4 *SB,
+                          const uint4 *Hc, double *Shat, hipStream_t s);
 // dL/dbeta from dL/dSt (z-blocked, times wz on read)
 hipError_t launch_betahat(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, int64_t upad,
                           const double *wl, const double *ql, const double *P, const double *Shat,

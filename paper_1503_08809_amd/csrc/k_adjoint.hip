@@ -9,7 +9,7 @@
 //     dL/dSt_u(z) = 3 Sum_{v,w} H[u,v,w] St_v(z) St_w(z).
 // Here H is evaluated entry by entry from G (each entry gathers the Gamma
 // entries it feeds; no atomics) straight into the operand order of the
-// block kernels (k_adjoint_f64.hip, k_adjoint_mx.hip) as
+// kernels (k_adjoint_f64.hip, k_adjoint_fac.hip) as
 // Hc[u][(v,w)] = 3 c_vw H[u,v,w] over pairs v <= w, and dL/dS = W^(1/3) dL/dSt.
 // Step c.  betahat_p(l, r) = Sum_{a, mu} [w_l qbar_a(l) P_l(mu)] Shat_ap(r, mu):
 //   per p and per parity of l, one GEMM with the (a, mu >= 0) depth, a
@@ -76,50 +76,50 @@ __device__ double adj_h(int kind, int np, int na, const int *__restrict__ inv_a,
     return h;
 }
 
-// Hc[u][(v,w)] = 3 c_vw H[u,v,w] (c = 2 for v < w, 1 for v = w, 0 for v > w)
-// split into BF16 hi and lo, in the A-operand order of the mixed adjoint
-// kernel: Hc[pair block][row block of 256][step][row tile][hi/lo][lane], a
-// lane holding rows 16-tile + lane % 16 and step pairs 8 (lane / 16) .. + 7.
 __device__ __forceinline__ uint32_t bf16_bits(float f)
 {
     const uint32_t u = __float_as_uint(f);
     return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
-__global__ void k_build_hc_mx(int kind, int U, int np, int na, const int *__restrict__ inv_a,
-                              const int *__restrict__ inv_p, const double *__restrict__ G, int tp,
-                              const int2 *__restrict__ pblocks, int npb, int nib, uint4 *__restrict__ Hc)
+// Hc[u][(v,w)] = 3 c_vw H[u,v,w] (c = 2 for v < w, 1 for v = w), split into
+// BF16 hi and lo, for the factored mixed kernel: per v, the w steps from the one
+// holding v to the last ([v_step_offset(v) + ws'][row block of 256][row
+// tile][hi/lo][lane], lane: row 16-tile + lane % 16, w = 32 ws + 8 (lane / 16)
+// .. + 7); entries with w < v are zero.  blockIdx.y = v.
+__global__ void k_build_hc_fac(int kind, int U, int np, int na, const int *__restrict__ inv_a,
+                               const int *__restrict__ inv_p, const double *__restrict__ G, int tp, int nws,
+                               int nib, uint4 *__restrict__ Hc)
 {
-    const int64_t n = (int64_t)npb * nib * 8 * 16 * 64;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int lane = (int)(e & 63), rt = (int)((e >> 6) & 15), ks = (int)((e >> 10) & 7);
-        const int64_t pbib = e >> 13;
-        const int ib = (int)(pbib % nib), pb = (int)(pbib / nib);
-        const int2 b = pblocks[pb];
-        const int u = ib * 256 + rt * 16 + (lane & 15);
-        float x[8];
+    const int v = blockIdx.y;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(e & 63), rt = (int)((e >> 6) & 15);
+    const int64_t r = e >> 10;
+    const int ib = (int)(r % nib), wsr = (int)(r / nib);
+    const int ws = (v >> 5) + wsr;
+    if (ws >= nws) return;
+    const int u = ib * 256 + rt * 16 + (lane & 15);
+    float x[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int pi = 32 * ks + 8 * (lane >> 4) + q;
-            const int v = b.x * 16 + (pi >> 4), w = b.y * 16 + (pi & 15);
-            double h = 0.0;
-            if (u < U && v < U && w < U && v <= w)
-                h = (v < w ? 6.0 : 3.0) * adj_h(kind, np, na, inv_a, inv_p, G, tp, u, v, w);
-            x[q] = (float)h;
-        }
-        uint32_t hi[4], lo[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t h0 = bf16_bits(x[2 * q]), h1 = bf16_bits(x[2 * q + 1]);
-            hi[q] = h0 | (h1 << 16);
-            lo[q] = bf16_bits(x[2 * q] - __uint_as_float(h0 << 16)) |
-                    (bf16_bits(x[2 * q + 1] - __uint_as_float(h1 << 16)) << 16);
-        }
-        uint4 *o = Hc + ((e >> 6) << 7) + lane;        // [.. row tile][hi/lo][lane]
-        o[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-        o[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    for (int q = 0; q < 8; ++q) {
+        const int w = 32 * ws + 8 * (lane >> 4) + q;
+        double h = 0.0;
+        if (u < U && w < U && w >= v)
+            h = (w > v ? 6.0 : 3.0) * adj_h(kind, np, na, inv_a, inv_p, G, tp, u, v, w);
+        x[q] = (float)h;
     }
+    uint32_t hi[4], lo[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t h0 = bf16_bits(x[2 * q]), h1 = bf16_bits(x[2 * q + 1]);
+        hi[q] = h0 | (h1 << 16);
+        lo[q] = bf16_bits(x[2 * q] - __uint_as_float(h0 << 16)) |
+                (bf16_bits(x[2 * q + 1] - __uint_as_float(h1 << 16)) << 16);
+    }
+    const int64_t st = v_step_offset(v, nws) + wsr;
+    uint4 *o = Hc + (((size_t)st * nib + ib) * 16 + rt) * 128 + lane;
+    o[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    o[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
 }
 
 // The same Hc in FP64, in the order of the FP64 adjoint kernel:
@@ -245,15 +245,14 @@ __global__ void k_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const doub
 
 }  // namespace
 
-hipError_t launch_build_hc_mixed(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
-                                 const double *G, int tp, const int2 *pblocks, int npb, int nib, uint4 *Hc,
-                                 hipStream_t s)
+hipError_t launch_build_hc_fac(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                               const double *G, int tp, int nib, uint4 *Hc, hipStream_t s)
 {
-    const int64_t n = (int64_t)npb * nib * 8 * 16 * 64;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_hc_mx, dim3((unsigned)blocks), dim3(256), 0, s, kind, U, np, na, inv_a, inv_p,
-                       G, tp, pblocks, npb, nib, Hc);
+    const int nws = (U + 31) / 32;
+    const int64_t n = (int64_t)nws * nib * 16 * 64;
+    if (U > 65535) return hipErrorInvalidValue;     // grid y limit
+    hipLaunchKernelGGL(k_build_hc_fac, dim3((unsigned)((n + 255) / 256), (unsigned)U), dim3(256), 0, s, kind, U,
+                       np, na, inv_a, inv_p, G, tp, nws, nib, Hc);
     return hipGetLastError();
 }
 

@@ -27,17 +27,8 @@
 // the group's rows in LDS (double-buffered, next chunk prefetched into
 // registers); each of the four waves owns 64 rows x 64 pairs.
 //
-// Mixed path (k_triple_mixed): v_mfma_f32_16x16x32_bf16 on a split of both
-// operands into high and low BF16 parts, x = x_hi + x_lo, keeping the three
-// products hi*hi + hi*lo + lo*hi of each term (the dropped lo*lo is ~2^-16
-// of the term).  Tasks are 4 column tiles x 256 rows; each wave owns 64 rows
-// and all 64 pairs, loads its A fragments (pre-split rows) straight from
-// memory, and generates one column tile of the product operand per 32-wide
-// z step (FP32 product of two FP32 rows, then split), shared with the other
-// waves through LDS.  Each r's mu sum is accumulated in FP32 by the matrix
-// cores and then added to the FP64 r sum held in T (the workgroup owns its
-// outputs, so this is a plain read-modify-write).  The mu sum of an r is
-// always complete before it enters the r sum (Sec. 2.2).
+// The mixed-precision kernel is in k_triple_mx.hip; this file also holds the
+// FP64 copy and BF16 split of the scaled rows that it reads.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -48,12 +39,9 @@ namespace mp {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // ---- shapes -----------------------------------------------------------------
 constexpr int F64_ROWBLOCK = 128, F64_TILES = 8, F64_GROUP_ROWS = 160;
-constexpr int MX_ROWBLOCK = 256, MX_TILES = 4, MX_GROUP_ROWS = 96;
 
 constexpr int ZC = 16;                       // z values per staged chunk (FP64)
 constexpr int LDSA = F64_ROWBLOCK + 1;       // padded LDS row lengths (doubles)
@@ -220,235 +208,11 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
         }
 }
 
-// ============================================================================
-// Mixed: split BF16 on matrix cores
-// ============================================================================
+// ---- operands of the mixed kernel ------------------------------------------
 __device__ __forceinline__ uint32_t bf16_rne_bits(float f)
 {
     const uint32_t u = __float_as_uint(f);
     return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-
-// one operand fragment: 8 BF16 high parts and 8 low parts
-struct Frag {
-    uint4 hi, lo;
-};
-
-__device__ __forceinline__ bf8 as_bf8(uint4 v)
-{
-    bf8 r;
-    __builtin_memcpy(&r, &v, sizeof(r));
-    return r;
-}
-
-// split 8 FP32 values into BF16 high parts (round to nearest even) and the
-// BF16 rounding of the exact remainders
-__device__ __forceinline__ Frag split8(const float v[8])
-{
-    uint32_t h[4], l[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t h0 = bf16_rne_bits(v[2 * i]), h1 = bf16_rne_bits(v[2 * i + 1]);
-        const float r0 = v[2 * i] - __uint_as_float(h0 << 16);
-        const float r1 = v[2 * i + 1] - __uint_as_float(h1 << 16);
-        h[i] = h0 | (h1 << 16);
-        l[i] = bf16_rne_bits(r0) | (bf16_rne_bits(r1) << 16);
-    }
-    Frag f;
-    f.hi = make_uint4(h[0], h[1], h[2], h[3]);
-    f.lo = make_uint4(l[0], l[1], l[2], l[3]);
-    return f;
-}
-
-constexpr int MX_KZ = 32;                    // z values per matrix-core step
-constexpr int MX_SRC_LD = MX_KZ + 4;         // padded LDS row (floats)
-
-__global__ __launch_bounds__(256) void k_triple_mixed(TripleArgs A, int nr, int kpr,
-                                                      const float *__restrict__ S32,
-                                                      const uint16_t *__restrict__ SA,
-                                                      double *__restrict__ T)
-{
-    constexpr int CT = MX_TILES;
-    __shared__ float Src[2][MX_GROUP_ROWS][MX_SRC_LD];
-    __shared__ uint4 Bb[2][CT][2][64];               // [buf][tile][hi/lo][lane]
-
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int task = task_of_block(blockIdx.x, A.ntasks);
-    const int2 tk = A.tasks[task];
-    const int g = tk.x, rb = tk.y;
-    const int t0 = A.group_tile0[g], nt = A.group_tile0[g + 1] - t0;
-    const int *grow = A.group_rows + (size_t)g * A.group_cap;
-    const int row0 = rb * MX_ROWBLOCK + wave * 64;   // this wave's 64 rows
-    const int n = lane & 15, zg = lane >> 4;
-
-    // the column tile this wave generates (tile index == wave); tiles past the
-    // group's end use valid rows (local 0) and are never stored
-    int gj = 0, gk = 0;
-    if (wave < nt) {
-        const int q = (t0 + wave) * 16 + n;
-        gj = A.pair_lj[q];
-        gk = A.pair_lk[q];
-    }
-    unsigned mask = 0;
-    for (int j = 0; j < CT; ++j) {
-        if (j >= nt) break;
-        const int mj = A.tile_maxj[t0 + j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (row0 + i * 16 <= mj) mask |= 1u << (i * CT + j);
-    }
-    mask = __builtin_amdgcn_readfirstlane(mask);
-    const bool active = mask != 0;                   // wave-uniform
-    // T blocks of this wave: tile j, row block (row0 >> 4) + i at tdst[j] + 256 i
-    double *tdst[CT];
-#pragma unroll
-    for (int j = 0; j < CT; ++j)
-        tdst[j] = T + ((size_t)(A.tile_off[t0 + (j < nt ? j : 0)] + (row0 >> 4)) << 8);
-
-    f4 acc[4][CT];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < CT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-    const int64_t nsteps = A.nz / MX_KZ;
-    // A fragments of step s: row row0 + 16 i + n, 8-z group zg, at
-    // SA[((s * upad + row) * 4 + zg) * 16]
-    size_t arow[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) arow[i] = ((size_t)(row0 + 16 * i + n) * 4 + zg) << 4;
-    const size_t astep = (size_t)A.upad << 6;        // uint16 per step
-    auto aload = [&](int64_t s, uint4 (&h)[4], uint4 (&l)[4]) {
-        const uint16_t *base = SA + (size_t)s * astep;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(base + arow[i]);
-            h[i] = p[0];
-            l[i] = p[1];
-        }
-    };
-    // source rows of the group (padded to MX_GROUP_ROWS with valid rows):
-    // 96 rows x 32 floats = 768 float4, three per thread
-    constexpr int SRC_PER = MX_GROUP_ROWS * 8 / 256;
-    size_t soff[SRC_PER];
-#pragma unroll
-    for (int i = 0; i < SRC_PER; ++i) {
-        const int idx = t + 256 * i;
-        soff[i] = ((size_t)grow[idx >> 3] << 5) + 4 * (idx & 7);
-    }
-    const size_t sstep = (size_t)A.upad << 5;         // floats per step
-    f4 sreg[SRC_PER];      // native vectors: HIP's float4 struct is not promoted to registers here
-    auto sload = [&](int64_t s) {
-        const float *base = S32 + (size_t)s * sstep;
-#pragma unroll
-        for (int i = 0; i < SRC_PER; ++i) sreg[i] = *reinterpret_cast<const f4 *>(base + soff[i]);
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < SRC_PER; ++i) {
-            const int idx = t + 256 * i;
-            *reinterpret_cast<f4 *>(&Src[buf][idx >> 3][4 * (idx & 7)]) = sreg[i];
-        }
-    };
-    auto bgen = [&](int buf) {
-        float v[8];
-        const float *pj = &Src[buf][gj][8 * zg];
-        const float *pk = &Src[buf][gk][8 * zg];
-        const float4 j0 = *reinterpret_cast<const float4 *>(pj), j1 = *reinterpret_cast<const float4 *>(pj + 4);
-        const float4 k0 = *reinterpret_cast<const float4 *>(pk), k1 = *reinterpret_cast<const float4 *>(pk + 4);
-        v[0] = j0.x * k0.x; v[1] = j0.y * k0.y; v[2] = j0.z * k0.z; v[3] = j0.w * k0.w;
-        v[4] = j1.x * k1.x; v[5] = j1.y * k1.y; v[6] = j1.z * k1.z; v[7] = j1.w * k1.w;
-        const Frag f = split8(v);
-        Bb[buf][wave][0][lane] = f.hi;
-        Bb[buf][wave][1][lane] = f.lo;
-    };
-
-    // prologue: sources of steps 0 and 1 in LDS, operand of step 0 generated
-    uint4 ah[4], al[4], nh[4], nl[4];
-    sload(0);
-    sstore(0);
-    sload(nsteps > 1 ? 1 : 0);
-    sstore(1);
-    lds_barrier();
-    bgen(0);
-    sload(nsteps > 2 ? 2 : nsteps - 1);
-    aload(0, ah, al);
-    lds_barrier();
-
-    int kin = 0;                                     // step within the current r
-    bool first_flush = true;
-    const int64_t last = nsteps - 1;
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const int buf = (int)(s & 1);
-        // Past the last step these clamp to it and produce values that are
-        // never used; keeping them unconditional keeps the loop free of
-        // branches around the register-resident staging.
-        bgen(buf ^ 1);                               // operand of step s + 1
-        aload(s + 1 < last ? s + 1 : last, nh, nl);
-        sstore(buf);                                 // sources of step s + 2
-        sload(s + 3 < last ? s + 3 : last);
-        if (active) {
-            bf8 bh[CT], bl[CT];
-#pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                bh[j] = as_bf8(Bb[buf][j][0][lane]);
-                bl[j] = as_bf8(Bb[buf][j][1][lane]);
-            }
-            // the three products, each over all tiles, so that consecutive
-            // matrix-core operations never depend on each other
-#pragma unroll
-            for (int j = 0; j < CT; ++j)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < CT; ++j)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < CT; ++j)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), bh[j], acc[i][j], 0, 0, 0);
-        }
-        if (++kin == kpr) {
-            // this r's mu sum is complete: add it to the FP64 r sum in T.
-            // All loads are issued before any add so their latencies overlap.
-            // (BF16 16x16x32 result layout: lane l, element q -> row 4(l/16) + q, column l%16)
-            kin = 0;
-            double old[4][CT][4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < CT; ++j)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        old[i][j][q] = 0.0;
-                        if (!first_flush && (mask & (1u << (i * CT + j))))
-                            old[i][j][q] = tdst[j][(size_t)(i * 256 + (4 * zg + q) * 16 + n)];
-                    }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < CT; ++j) {
-                    if (mask & (1u << (i * CT + j))) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            tdst[j][(size_t)(i * 256 + (4 * zg + q) * 16 + n)] =
-                                old[i][j][q] + (double)acc[i][j][q];
-                    }
-                    acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-                }
-            first_flush = false;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ah[i] = nh[i];
-            al[i] = nl[i];
-        }
-        lds_barrier();
-    }
 }
 
 __global__ void k_split_bf16(int64_t nblk, const double *__restrict__ St, float *__restrict__ S32,
@@ -524,13 +288,6 @@ void triple_f64_shape(int &rb, int &tpg, int &gr)
     rb = F64_ROWBLOCK;
     tpg = F64_TILES;
     gr = F64_GROUP_ROWS;
-}
-
-void triple_mixed_shape(int &rb, int &tpg, int &gr)
-{
-    rb = MX_ROWBLOCK;
-    tpg = MX_TILES;
-    gr = MX_GROUP_ROWS;
 }
 
 hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group_cap,
@@ -675,19 +432,6 @@ hipError_t launch_triple_f64(const TriplePlan &plan, int64_t upad, int64_t ldz, 
         return hipErrorInvalidValue;
     if (plan.ntasks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_triple_f64, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, upad, ldz), St, T);
-    return hipGetLastError();
-}
-
-hipError_t launch_triple_mixed(const TriplePlan &plan, int64_t upad, int64_t ldz, int nr, int nmu_pad,
-                               const float *S32, const uint16_t *SA, double *T, hipStream_t s)
-{
-    if (nmu_pad % MX_KZ != 0 || ldz != (int64_t)nr * nmu_pad || upad % MX_ROWBLOCK != 0 ||
-        upad < plan.U || plan.rowblock != MX_ROWBLOCK || plan.tiles_per_group != MX_TILES ||
-        plan.group_rows != MX_GROUP_ROWS)
-        return hipErrorInvalidValue;
-    if (plan.ntasks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_triple_mixed, dim3(plan.ntasks), dim3(256), 0, s, args_of(plan, upad, ldz), nr,
-                       nmu_pad / MX_KZ, S32, SA, T);
     return hipGetLastError();
 }
 
