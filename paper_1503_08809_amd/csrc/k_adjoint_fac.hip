@@ -197,11 +197,9 @@ __global__ __launch_bounds__(512) void k_adj_fac(FacArgs A, const double *__rest
         // loads only make this stricter)
         __builtin_amdgcn_s_waitcnt(0x0f76);                             // vmcnt(6)
         __builtin_amdgcn_s_barrier();
-        // every wave is past step st - 1: its slot can be refilled
-        issue_next(rn);
         const bool vlast = ws == nws - 1;
+        uint4 ah[RB], al[RB], fh[TW], fl[TW];
         if (active) {
-            uint4 ah[RB], al[RB], fh[TW], fl[TW];
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 ah[i] = r[(RB * rg + i) * 128 + lane];
@@ -212,6 +210,14 @@ __global__ __launch_bounds__(512) void k_adj_fac(FacArgs A, const double *__rest
                 fh[j] = r[SLOT_A + (TW * ch + j) * 128 + lane];
                 fl[j] = r[SLOT_A + (TW * ch + j) * 128 + 64 + lane];
             }
+        }
+        // every wave is past step st - 1: its slot can be refilled.  Issued
+        // after this step's LDS reads, so that no wait the compiler places
+        // before those reads covers these loads.
+        __builtin_amdgcn_sched_barrier(0);
+        issue_next(rn);
+        __builtin_amdgcn_sched_barrier(0);
+        if (active) {
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
 #pragma unroll
