@@ -14,10 +14,13 @@
 // wave w owns rows 64 (w % 4) .. + 63 and column tiles 4 (w / 4) .. + 3
 // (16 z each); per step it issues 4 x 4 tiles x 3 products.  Both operands of
 // a step (A: Hc, 256 rows x 32 w, 32 KB; B: the pre-split rows, 32 w x 128 z,
-// 16 KB) are copied from memory straight into LDS (global_load_lds, no
+// 16 KB) are copied from memory straight into LDS (buffer_load ... lds, no
 // registers) two steps ahead through a ring of three slots, one barrier per
-// step.  Hc is ordered [v][w step][row block] so that the workgroups of one
-// XCD (same row block, neighbouring z tiles) read it through one L2.
+// step; each wave reads its operands in the order its matrix-core operations
+// take them, so the first starts once three reads are back.  Hc is ordered
+// [v][w step][row block]; the workgroups of one XCD take the row blocks of
+// neighbouring z tiles in turn, so each Hc tile and each block of split rows
+// is read through one L2 by several of them.
 //
 // Arithmetic: A_lo B_hi + A_hi B_lo + A_hi B_hi per term on
 // v_mfma_f32_16x16x32_bf16, FP32 sums over w (D_v) and over up to kFlushV
@@ -66,13 +69,19 @@ struct FacArgs {
     int64_t upad;
 };
 
-// LDS DMA (global_load_lds_dwordx4): each lane's 16 bytes land at
-// base + 16 lane, so one instruction moves one 1 KB operand half (hi or lo)
-// of a fragment, already in the order the lanes read it back
-__device__ __forceinline__ void dma16(const uint4 *g, uint4 *lds_base)
+// LDS DMA in buffer form (buffer_load_dwordx4 ... lds): each lane's 16 bytes
+// land at lds_base + 16 lane, so one instruction moves one 1 KB operand half
+// (hi or lo) of a fragment, already in the order the lanes read it back.  The
+// buffer form, unlike the global one, lets the compiler keep counting the LDS
+// reads issued before it exactly, so a matrix-core operation waits only for
+// its own operands.  `rs` covers the wave's bytes of the step (reads outside
+// it return zero); `soff` selects the fragment inside it.
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, uint4 *lds_base)
 {
-    __builtin_amdgcn_global_load_lds((const void *)g, (__attribute__((address_space(3))) void *)lds_base, 16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)lds_base, 16, voff, soff,
+                                             0, 0);
 }
+constexpr int kBufWord3 = 0x00020000;         // descriptor word 3: 32-bit data format, raw access
 
 constexpr int RING = 3;                       // steps in flight (LDS slots)
 constexpr int SLOT_A = (AI / 16) * 128;       // uint4 of A (Hc) per slot: row tiles x hi/lo x lanes
@@ -98,7 +107,9 @@ __global__ __launch_bounds__(512) void k_adj_fac(FacArgs A, const double *__rest
         const int base = ntasks >> 3, rem = ntasks & 7;
         return x * base + (x < rem ? x : rem) + idx;
     }();
-    const int ib = task / A.nzt, zt = task % A.nzt;
+    // consecutive tasks (co-resident on one XCD) take the row blocks of one
+    // z tile in turn: the XCD's workgroups share both operand streams
+    const int ib = task % A.nib, zt = task / A.nib;
     const int64_t zb0 = (int64_t)zt * ZBW;
     const int u0 = ib * AI + rg * 16 * RB;
     const bool active = u0 < A.U;
@@ -116,16 +127,19 @@ __global__ __launch_bounds__(512) void k_adj_fac(FacArgs A, const double *__rest
 
     // this wave's share of a step's operands (6 DMA instructions): A row
     // tiles 2 wave, 2 wave + 1 and B column tile `wave`, hi and lo each
-    const uint4 *bsrc = SB + ((size_t)(zb0 + (wave >> 1)) * nws * 2 + (wave & 1)) * 128 + lane;
+    const uint4 *bsrc = SB + ((size_t)(zb0 + (wave >> 1)) * nws * 2 + (wave & 1)) * 128;
+    const uint32_t voff = (uint32_t)lane * 16;
     auto issue = [&](int64_t st, int ws, uint4 *r) {
-        const uint4 *a = Hc + (((size_t)st * A.nib + ib) * (AI / 16) + 2 * wave) * 128 + lane;
-        dma16(a, r + (2 * wave) * 128);
-        dma16(a + 64, r + (2 * wave) * 128 + 64);
-        dma16(a + 128, r + (2 * wave + 1) * 128);
-        dma16(a + 192, r + (2 * wave + 1) * 128 + 64);
-        const uint4 *b = bsrc + (size_t)ws * 256;
-        dma16(b, r + SLOT_A + wave * 128);
-        dma16(b + 64, r + SLOT_A + wave * 128 + 64);
+        const uint4 *a = Hc + (((size_t)st * A.nib + ib) * (AI / 16) + 2 * wave) * 128;
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void *)a, 0, 4096, kBufWord3);
+        dma16(ra, voff, 0, r + (2 * wave) * 128);
+        dma16(ra, voff, 1024, r + (2 * wave) * 128 + 64);
+        dma16(ra, voff, 2048, r + (2 * wave + 1) * 128);
+        dma16(ra, voff, 3072, r + (2 * wave + 1) * 128 + 64);
+        const __amdgpu_buffer_rsrc_t rb =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(bsrc + (size_t)ws * 256), 0, 2048, kBufWord3);
+        dma16(rb, voff, 0, r + SLOT_A + wave * 128);
+        dma16(rb, voff, 1024, r + SLOT_A + wave * 128 + 64);
     };
     // St_v at this lane's columns (FP32): z = zb0 * 32 + 16 (TW ch + j) + lane % 16
     const int zl0 = ch * 16 * TW + (lane & 15);
@@ -200,15 +214,17 @@ __global__ __launch_bounds__(512) void k_adj_fac(FacArgs A, const double *__rest
         const bool vlast = ws == nws - 1;
         uint4 ah[RB], al[RB], fh[TW], fl[TW];
         if (active) {
+            // in the order the matrix-core operations take them
+            al[0] = r[(RB * rg) * 128 + 64 + lane];
 #pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                ah[i] = r[(RB * rg + i) * 128 + lane];
+            for (int j = 0; j < TW; ++j) fh[j] = r[SLOT_A + (TW * ch + j) * 128 + lane];
+            ah[0] = r[(RB * rg) * 128 + lane];
+#pragma unroll
+            for (int j = 0; j < TW; ++j) fl[j] = r[SLOT_A + (TW * ch + j) * 128 + 64 + lane];
+#pragma unroll
+            for (int i = 1; i < RB; ++i) {
                 al[i] = r[(RB * rg + i) * 128 + 64 + lane];
-            }
-#pragma unroll
-            for (int j = 0; j < TW; ++j) {
-                fh[j] = r[SLOT_A + (TW * ch + j) * 128 + lane];
-                fl[j] = r[SLOT_A + (TW * ch + j) * 128 + 64 + lane];
+                ah[i] = r[(RB * rg + i) * 128 + lane];
             }
         }
         // every wave is past step st - 1: its slot can be refilled.  Issued
