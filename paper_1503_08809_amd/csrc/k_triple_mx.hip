@@ -26,10 +26,11 @@
 // Eight waves (two per SIMD): wave w owns rows 32 (w % 4) .. + 31 of the
 // task and pair tiles 8 (w / 4) .. + 7.  Per 32-wide z step a wave issues
 // 2 row blocks x 8 pair tiles x 3 products = 48 matrix-core operations,
-// generates 2 of the 16 pair tiles for the next step and shares them through
-// LDS (double-buffered, one barrier per step), loads its A fragments straight
-// from memory, and the first four waves stage the 32 source rows of the step
-// after next.
+// reading each pair tile from LDS two tiles ahead of its use; generates 2 of
+// the 16 pair tiles for the next step (its k rows read once for both) and
+// shares them through LDS (double-buffered, one barrier per step); loads its
+// A fragments straight from memory two steps ahead (two register sets); and
+// the first four waves stage the 32 source rows of the step after next.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -127,8 +128,9 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
     // wave-uniform base keep the addressing in scalar registers plus one VGPR
     const uint32_t aoff = ((uint32_t)(i0 + n) * 4 + zg) << 4;     // uint16 units
     const size_t astep = (size_t)A.upad << 6;
-    uint4 ah[RB], al[RB];
-    auto aload = [&](int64_t s) {
+    // two sets: step s uses set s % 2, whose loads were issued two steps ahead
+    uint4 ah0[RB], al0[RB], ah1[RB], al1[RB];
+    auto aload = [&](int64_t s, uint4 (&ah)[RB], uint4 (&al)[RB]) {
         const uint16_t *base = SA + (size_t)s * astep;
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
@@ -150,10 +152,15 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
     auto sstore = [&](int buf) {
         if (stager) *reinterpret_cast<f4 *>(&Src[buf][srow][4 * sq]) = sreg;
     };
-    // this wave generates pair tiles 2 wave and 2 wave + 1 (tile = j local)
-    auto bgen_tile = [&](int buf, int q) {
+    // this wave generates pair tiles 2 wave and 2 wave + 1 (tile = j local);
+    // the k values (this lane's k row, 8 z) are read once for both
+    f4 k0v, k1v;
+    auto bgen_k = [&](int buf) {
         const float *pk = &Src[buf][BJ + n][8 * zg];
-        const f4 k0v = *reinterpret_cast<const f4 *>(pk), k1v = *reinterpret_cast<const f4 *>(pk + 4);
+        k0v = *reinterpret_cast<const f4 *>(pk);
+        k1v = *reinterpret_cast<const f4 *>(pk + 4);
+    };
+    auto bgen_tile = [&](int buf, int q) {
         const int tile = 2 * wave + q;
         const float *pj = &Src[buf][tile][8 * zg];
         const f4 j0v = *reinterpret_cast<const f4 *>(pj), j1v = *reinterpret_cast<const f4 *>(pj + 4);
@@ -163,9 +170,9 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
             v[e] = j0v[e] * k0v[e];
             v[4 + e] = j1v[e] * k1v[e];
         }
-            uint32_t h[4], l[4];
+        uint32_t h[4], l[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], h[e], l[e]);
+        for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], h[e], l[e]);
         Bb[buf][tile][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
         Bb[buf][tile][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
     };
@@ -181,31 +188,39 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
     sload(nsteps > 1 ? 1 : 0);
     sstore(1);
     lds_barrier();
+    bgen_k(0);
     bgen_tile(0, 0);
     bgen_tile(0, 1);
     sload(nsteps > 2 ? 2 : last);
-    aload(0);
+    aload(0, ah0, al0);
+    aload(nsteps > 1 ? 1 : 0, ah1, al1);
     lds_barrier();
 
     int kin = 0;
     bool first = true;
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const int buf = (int)(s & 1);
+    int64_t s = 0;
+    // one step with parity P (LDS buffers and A set P); false when done
+    auto step = [&](auto par) -> bool {
+        constexpr int P = decltype(par)::value;
+        constexpr int buf = P;
+        uint4(&ah)[RB] = P ? ah1 : ah0;
+        uint4(&al)[RB] = P ? al1 : al0;
         // past the last step these clamp to it; their results are never used
         sstore(buf);                                       // sources of step s + 2
         sload(s + 3 < last ? s + 3 : last);
         if (active) {
             // software pipeline over this wave's 8 pair tiles: the operand of
-            // tile j + 1 is read from LDS while tile j's 6 matrix-core
+            // tile j + 2 is read from LDS while tile j's 6 matrix-core
             // operations run; this wave's 2 pair tiles of step s + 1 are
             // generated after tiles 3 and 7 (VALU work under the matrix cores)
             uint4 bh = Bb[buf][th * TW][0][lane], bl = Bb[buf][th * TW][1][lane];
+            uint4 mbh = Bb[buf][th * TW + 1][0][lane], mbl = Bb[buf][th * TW + 1][1][lane];
 #pragma unroll
             for (int j = 0; j < TW; ++j) {
-                uint4 nbh = bh, nbl = bl;
-                if (j + 1 < TW) {
-                    nbh = Bb[buf][th * TW + j + 1][0][lane];
-                    nbl = Bb[buf][th * TW + j + 1][1][lane];
+                uint4 nbh = mbh, nbl = mbl;
+                if (j + 2 < TW) {
+                    nbh = Bb[buf][th * TW + j + 2][0][lane];
+                    nbl = Bb[buf][th * TW + j + 2][1][lane];
                 }
                 const bf8 h8 = as_bf8(bh), l8 = as_bf8(bl);
 #pragma unroll
@@ -217,12 +232,16 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
 #pragma unroll
                 for (int i = 0; i < RB; ++i)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), h8, acc[i][j], 0, 0, 0);
+                if (j == 3) bgen_k(buf ^ 1);
                 if ((j & 3) == 3) bgen_tile(buf ^ 1, j >> 2);      // operand of step s + 1
                 __builtin_amdgcn_sched_barrier(0);
-                bh = nbh;
-                bl = nbl;
+                bh = mbh;
+                bl = mbl;
+                mbh = nbh;
+                mbl = nbl;
             }
         } else {
+            bgen_k(buf ^ 1);
             bgen_tile(buf ^ 1, 0);
             bgen_tile(buf ^ 1, 1);
         }
@@ -262,9 +281,14 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
                 for (int j = 0; j < TW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
             first = false;
         }
-        // A fragments of step s + 1 (the other wave of the SIMD covers the latency)
-        aload(s + 1 < last ? s + 1 : last);
+        // A fragments of step s + 2 into the set this step has finished with
+        aload(s + 2 < last ? s + 2 : last, ah, al);
         lds_barrier();
+        return ++s < nsteps;
+    };
+    for (;;) {
+        if (!step(std::integral_constant<int, 0>())) break;
+        if (!step(std::integral_constant<int, 1>())) break;
     }
 }
 
