@@ -212,10 +212,11 @@ modal_status modal_gamma(modal_ctx ctx, const modal_grid *grid, const modal_prob
  * triple (for SYMMETRIC: a sorted triple), else MODAL_ERR_SHAPE.
  * MODAL_FP64 runs every adjoint stage in FP64; MODAL_MIXED runs the adjoint
  * of Eq. (2D) (dL/dS from dL/dGamma, the dominant stage) on BF16 matrix cores
- * with split operands, FP32 partial sums over 8192 pair terms and FP64
- * accumulation, and the other adjoint stages in FP64.  The workspace holds,
- * besides the forward's, dL/dS (as large as S) and the tensor dL/dT in
- * blocks (about 4 U^3 bytes for FP64, 2 U^3 for MIXED, U = np * na). */
+ * with split operands, FP32 partial sums (over the w of one v, then over 64
+ * values of v) and FP64 accumulation, and the other adjoint stages in FP64.
+ * The workspace holds, besides the forward's, dL/dS (as large as S) and the
+ * tensor dL/dT in blocks (about 4 U^3 bytes for FP64, 2 U^3 for MIXED,
+ * U = np * na). */
 modal_status modal_gamma_backward(modal_ctx ctx, const modal_grid *grid,
                                   const modal_problem *prob, modal_precision prec,
                                   const double *dgamma, double *dqk, double *ddelta);
