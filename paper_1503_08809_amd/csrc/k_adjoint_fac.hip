@@ -17,7 +17,8 @@
 // 16 KB) are copied from memory straight into LDS (buffer_load ... lds, no
 // registers) two steps ahead through a ring of three slots, one barrier per
 // step; each wave reads its operands in the order its matrix-core operations
-// take them, so the first starts once three reads are back.  Hc is ordered
+// take them, so the first starts once three reads are back, and issues its
+// copies for the step after next behind its first row tile's operations.  Hc is ordered
 // [v][w step][row block]; the workgroups of one XCD take the row blocks of
 // neighbouring z tiles in turn, so each Hc tile and each block of split rows
 // is read through one L2 by several of them.
@@ -213,6 +214,17 @@ __global__ __launch_bounds__(512) void k_adj_fac(FacArgs A, const double *__rest
         __builtin_amdgcn_s_barrier();
         const bool vlast = ws == nws - 1;
         uint4 ah[RB], al[RB], fh[TW], fl[TW];
+        auto rows = [&](int i) {
+#pragma unroll
+            for (int j = 0; j < TW; ++j)
+                D[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), as_bf8(fh[j]), D[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < TW; ++j)
+                D[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), as_bf8(fl[j]), D[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < TW; ++j)
+                D[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), as_bf8(fh[j]), D[i][j], 0, 0, 0);
+        };
         if (active) {
             // in the order the matrix-core operations take them
             al[0] = r[(RB * rg) * 128 + 64 + lane];
@@ -226,26 +238,19 @@ __global__ __launch_bounds__(512) void k_adj_fac(FacArgs A, const double *__rest
                 al[i] = r[(RB * rg + i) * 128 + 64 + lane];
                 ah[i] = r[(RB * rg + i) * 128 + lane];
             }
+            rows(0);
         }
         // every wave is past step st - 1: its slot can be refilled.  Issued
-        // after this step's LDS reads, so that no wait the compiler places
-        // before those reads covers these loads.
+        // after this step's LDS reads (so that no wait the compiler places
+        // before those reads covers these loads) and after the first row
+        // tile's operations (so that no wave waits for the copy queue before
+        // its first operation).
         __builtin_amdgcn_sched_barrier(0);
         issue_next(rn);
         __builtin_amdgcn_sched_barrier(0);
         if (active) {
 #pragma unroll
-            for (int i = 0; i < RB; ++i) {
-#pragma unroll
-                for (int j = 0; j < TW; ++j)
-                    D[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), as_bf8(fh[j]), D[i][j], 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < TW; ++j)
-                    D[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), as_bf8(fl[j]), D[i][j], 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < TW; ++j)
-                    D[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), as_bf8(fh[j]), D[i][j], 0, 0, 0);
-            }
+            for (int i = 1; i < RB; ++i) rows(i);
             if (vlast) {
                 // D_v is complete: out += St_v(z) D_v(z), then D = 0
 #pragma unroll
