@@ -159,9 +159,9 @@ hipError_t launch_build_hc_fac(int kind, int U, int np, int na, const int *inv_a
 hipError_t launch_split_b(int64_t nzb, int U, int64_t upad, const double *St, uint4 *SB, hipStream_t s);
 hipError_t launch_adj_fac(int U, int64_t upad, int64_t nzb, const double *St, const uint4 *SB,
                           const uint4 *Hc, double *Shat, hipStream_t s);
-// dL/dbeta from dL/dSt (z-blocked, times wz on read)
+// dL/dbeta from dL/dSt (z-blocked; folded over +-mu and scaled by wz in place)
 hipError_t launch_betahat(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, int64_t upad,
-                          const double *wl, const double *ql, const double *P, const double *Shat,
+                          const double *wl, const double *ql, const double *P, double *Shat,
                           const double *wz, double *bhat, hipStream_t s);
 hipError_t launch_ahat(int nl, int l0, int lmin, int L, int np, int nk, int nr, const double *bhat,
                        const double *J, double *Ahat, hipStream_t s);

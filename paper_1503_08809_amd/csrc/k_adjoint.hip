@@ -161,37 +161,63 @@ struct DivBy {
     __device__ int quot(int n) const { return (int)((double)n * inv + 0x1p-20); }
 };
 
+// The mu fold of X = W^(1/3) dL/dSt, in place, once for both parities: for
+// each row u, r and node pair (+mu, -mu) = (ioff + jj, nh - 1 - jj), the
+// position of +mu receives X(+mu) + X(-mu) and the position of -mu receives
+// X(+mu) - X(-mu); the node mu = 0 (odd nmu: its own mirror) keeps X(0).
+__global__ void k_fold_mu(int U, int nr, int ldmu, int nh, int ioff, int64_t upad, const double *__restrict__ wz,
+                          double *__restrict__ Shat)
+{
+    const int64_t n = (int64_t)U * nr * nh;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int jj = (int)(e % nh);
+        const int64_t t = e / nh;
+        const int r = (int)(t % nr);
+        const int64_t u = t / nr;
+        const int64_t zp = (int64_t)r * ldmu + ioff + jj, zm = (int64_t)r * ldmu + nh - 1 - jj;
+        const int64_t ip = (((zp >> 5) * upad + u) << 5) + (zp & 31);
+        const double xp = wz[zp] * Shat[ip];
+        if (zp == zm) {
+            Shat[ip] = xp;
+        } else {
+            const int64_t im = (((zm >> 5) * upad + u) << 5) + (zm & 31);
+            const double xm = wz[zm] * Shat[im];
+            Shat[ip] = xp + xm;
+            Shat[im] = xp - xm;
+        }
+    }
+}
+
 struct BetaHatParOp {
     static constexpr bool a_k_fast = true;    // (a, mu >= 0) with mu contiguous
     static constexpr bool b_k_fast = true;
     int M, N, K;                              // rows of this parity, nr, na * nh
     int np, ldmu, nh, ioff, L, li0;
     DivBy bynh;                               // kk -> (a, mu index)
-    double sgn;                               // (-1)^l of these rows
+    int odd;                                  // l odd for these rows
     int64_t upad;
-    const double *wl, *ql, *P, *Shat, *wz;
+    const double *wl, *ql, *P, *Shat;
     double *bhat;
     struct RawA { double w, q, p; };
-    struct RawB { double wp, sp, wm, sm, cp, cm; };
+    struct RawB { double x, c; };
     __device__ RawA fa(int, int m, int kk) const
     {
         const int ia = bynh.quot(kk), jj = kk - ia * nh, li = li0 + 2 * m;
         return RawA{wl[li], ql[(size_t)ia * L + li], P[(size_t)li * ldmu + ioff + jj]};
     }
     __device__ double ma(const RawA &v) const { return v.w * v.q * v.p; }
-    // X(+mu) + sgn X(-mu), X = W^(1/3) dL/dSt at node ioff + jj and its mirror;
-    // at the node mu = 0 (its own mirror) X counts once, and only for even l
+    // X(+mu) + (-1)^l X(-mu) from the folded array: at the position of +mu
+    // for even l, of -mu for odd l; at the node mu = 0 X counts once, and
+    // only for even l
     __device__ RawB fb(int p, int kk, int r) const
     {
         const int ia = bynh.quot(kk), jj = kk - ia * nh;
         const size_t u = (size_t)ia * np + p;
-        const int64_t zp = (int64_t)r * ldmu + ioff + jj, zm = (int64_t)r * ldmu + nh - 1 - jj;
-        const bool centre = zp == zm;
-        return RawB{wz[zp], Shat[(((size_t)(zp >> 5) * upad + u) << 5) + (zp & 31)],
-                    wz[zm], Shat[(((size_t)(zm >> 5) * upad + u) << 5) + (zm & 31)],
-                    centre && sgn < 0.0 ? 0.0 : 1.0, centre ? 0.0 : sgn};
+        const int zo = odd ? nh - 1 - jj : ioff + jj;
+        const int64_t z = (int64_t)r * ldmu + zo;
+        return RawB{Shat[(((size_t)(z >> 5) * upad + u) << 5) + (z & 31)], odd && ioff + jj == zo ? 0.0 : 1.0};
     }
-    __device__ double mb(const RawB &v) const { return v.cp * v.wp * v.sp + v.cm * v.wm * v.sm; }
+    __device__ double mb(const RawB &v) const { return v.c * v.x; }
     __device__ void store(int p, int m, int r, double v) const
     {
         bhat[((size_t)p * L + li0 + 2 * m) * N + r] = v;
@@ -269,17 +295,26 @@ hipError_t launch_build_hc_f64(int kind, int U, int np, int na, const int *inv_a
 }
 
 hipError_t launch_betahat(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, int64_t upad,
-                          const double *wl, const double *ql, const double *P, const double *Shat,
+                          const double *wl, const double *ql, const double *P, double *Shat,
                           const double *wz, double *bhat, hipStream_t s)
 {
-    // rows of each parity of l: li with (lmin + li) even, then odd
     const int nh = (nmu + 1) / 2, ioff = nmu - nh;
+    {
+        const int64_t n = (int64_t)na * np * nr * nh;
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
+        if (blocks > 0)
+            hipLaunchKernelGGL(k_fold_mu, dim3((unsigned)blocks), dim3(256), 0, s, na * np, nr, ldmu, nh, ioff, upad,
+                               wz, Shat);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // rows of each parity of l: li with (lmin + li) even, then odd
     for (int par = 0; par < 2; ++par) {
         const int li0 = (par - lmin) & 1;
         const int rows = L > li0 ? (L - li0 + 1) / 2 : 0;
         if (rows == 0) continue;
-        BetaHatParOp op{rows, nr, na * nh, np, ldmu, nh, ioff, L, li0, DivBy{nh, 1.0 / nh}, par ? -1.0 : 1.0,
-                        upad, wl, ql, P, Shat, wz, bhat};
+        BetaHatParOp op{rows, nr, na * nh, np, ldmu, nh, ioff, L, li0, DivBy{nh, 1.0 / nh}, par,
+                        upad, wl, ql, P, Shat, bhat};
         const hipError_t e = run(op, np, s);
         if (e != hipSuccess) return e;
     }
