@@ -179,6 +179,9 @@ def main() -> int:
     print(f"[bench] inputs for {cfg.name} in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
           flush=True)
     ctx = mp.Context(0)
+    # the inputs never change: the adjoint takes the forward's tables (steps
+    # a-c) instead of recomputing them, as an autograd backward would
+    ctx.set_forward_reuse(True)
     pr = mp.projection_from_inputs(ctx, inp)
     out = ctx.empty(inp.tri_a.shape[0], inp.tri_p.shape[0])
     W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))

@@ -137,6 +137,19 @@ const char *modal_last_error(modal_ctx ctx);
  * returns MODAL_ERR_OOM. */
 modal_status modal_set_workspace_limit(modal_ctx ctx, size_t bytes);
 
+/* Reuse of the forward tables by modal_gamma_backward (off by default).
+ * When on, modal_gamma_backward takes the tables of steps a-c (the GL rule,
+ * P_l, the weights and the scaled S rows) from the context instead of
+ * recomputing them, if the context's previous call was modal_gamma or
+ * modal_gamma_backward with the same grid and problem: every field equal,
+ * pointers included.  The caller guarantees that the arrays behind those
+ * pointers have not changed since that call; any other call in between
+ * (except modal_set_forward_reuse, modal_set_workspace_limit,
+ * modal_enable_timing, modal_stage_times and modal_workspace_bytes) makes the
+ * backward recompute them.  The adjoint of the k contraction regenerates
+ * j_l either way. */
+modal_status modal_set_forward_reuse(modal_ctx ctx, int on);
+
 /* Device bytes the context would hold for modal_gamma on this problem. */
 modal_status modal_workspace_bytes(modal_ctx ctx, const modal_grid *grid,
                                    const modal_problem *prob, modal_precision prec,

@@ -29,6 +29,44 @@ struct Buf {
     size_t n = 0;
 };
 
+struct Grid {
+    const double *k, *wk, *r, *wr, *mu, *wmu;
+};
+
+// Steps a-c of the forward projection: GL rule, Legendre table, weights,
+// beta (Bessel chunks) and the scaled, z-blocked S rows.
+struct Forward {
+    Grid G;
+    const double *delta, *qk, *cl, *ql;
+    double *P, *wl, *wz, *beta, *St;
+};
+
+// The forward tables of the last modal_gamma (or recomputing
+// modal_gamma_backward) call, kept for a later modal_gamma_backward when the
+// caller has enabled reuse: valid only until any other call, and only for the
+// same grid and problem (every field, pointers included).
+struct FwdCache {
+    bool valid = false, was_valid = false;
+    modal_grid g{};
+    modal_problem p{};
+    Forward f{};
+    int next_in = 0;                   // host-input slots its staging used
+};
+
+bool same_inputs(const modal_grid &a, const modal_grid &b)
+{
+    return a.lmin == b.lmin && a.lmax == b.lmax && a.nk == b.nk && a.k == b.k && a.wk == b.wk && a.nr == b.nr &&
+           a.r == b.r && a.wr == b.wr && a.nmu == b.nmu && a.mu == b.mu && a.wmu == b.wmu &&
+           a.allow_inexact_gl == b.allow_inexact_gl;
+}
+
+bool same_inputs(const modal_problem &a, const modal_problem &b)
+{
+    return a.delta == b.delta && a.cl == b.cl && a.np == b.np && a.qk == b.qk && a.na == b.na && a.ql == b.ql &&
+           a.v_power == b.v_power && a.kind == b.kind && a.ta == b.ta && a.tri_a == b.tri_a && a.tp == b.tp &&
+           a.tri_p == b.tri_p;
+}
+
 }  // namespace
 
 struct modal_ctx_s {
@@ -41,6 +79,8 @@ struct modal_ctx_s {
     TriplePlan plan64;                 // triple-product plan of the FP64 kernel
     BTPlan planbt;                     // block-triple plan of the mixed kernel
     bool timing = false;
+    bool reuse_fwd = false;            // modal_set_forward_reuse
+    FwdCache fwd;
     // per stage: a pool of (start, end) event pairs; the first `used` belong
     // to the last call (chunked stages record one pair per chunk)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MODAL_NSTAGES];
@@ -319,6 +359,10 @@ modal_status guarded(modal_ctx c, F &&f)
         return MODAL_ERR_INVALID_ARG;
     }
     c->next_in = 0;
+    // any call may overwrite the workspace: only modal_gamma and
+    // modal_gamma_backward set the forward tables valid again
+    c->fwd.was_valid = c->fwd.valid;
+    c->fwd.valid = false;
     try {
         hipError_t e = hipSetDevice(c->device);
         if (e != hipSuccess) fail(c, MODAL_ERR_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
@@ -338,9 +382,6 @@ modal_status guarded(modal_ctx c, F &&f)
 }
 
 // ---- shared pipeline pieces ---------------------------------------------------
-struct Grid {
-    const double *k, *wk, *r, *wr, *mu, *wmu;
-};
 
 Grid stage_grid(modal_ctx c, const modal_grid *g, const Dims &d)
 {
@@ -401,14 +442,6 @@ void run_beta(modal_ctx c, const modal_grid *g, const Dims &d, const Grid &G, co
 // rowscale pointer arithmetic above: the emit kernel indexes
 // rowscale[(l - lrow0) * nk + k] with lrow0 = llo, so the pointer is offset to
 // row llo of delta.
-
-// Steps a-c of the forward projection: GL rule, Legendre table, weights,
-// beta (Bessel chunks) and the scaled, z-blocked S rows.
-struct Forward {
-    Grid G;
-    const double *delta, *qk, *cl, *ql;
-    double *P, *wl, *wz, *beta, *St;
-};
 
 Forward run_forward(modal_ctx c, const modal_grid *g, const modal_problem *p, const Dims &d)
 {
@@ -603,6 +636,13 @@ modal_status modal_set_workspace_limit(modal_ctx c, size_t bytes)
     return MODAL_OK;
 }
 
+modal_status modal_set_forward_reuse(modal_ctx c, int on)
+{
+    if (!c) return MODAL_ERR_INVALID_ARG;
+    c->reuse_fwd = on != 0;
+    return MODAL_OK;
+}
+
 modal_status modal_enable_timing(modal_ctx c, int on)
 {
     if (!c) return MODAL_ERR_INVALID_ARG;
@@ -639,6 +679,7 @@ modal_status modal_workspace_bytes(modal_ctx c, const modal_grid *g, const modal
                                    modal_precision prec, size_t *bytes)
 {
     return guarded(c, [&] {
+        c->fwd.valid = c->fwd.was_valid;          // reads no device memory
         need(c, bytes != nullptr, MODAL_ERR_INVALID_ARG, "bytes is NULL");
         check_prec(c, prec);
         Dims d = check_grid(c, g, false);
@@ -795,9 +836,11 @@ modal_status modal_gamma(modal_ctx c, const modal_grid *g, const modal_problem *
         need(c, gamma != nullptr || (int64_t)p->ta * p->tp == 0, MODAL_ERR_INVALID_ARG, "gamma is NULL");
         OutBuf o = dev_out(c, gamma, (size_t)p->ta * p->tp, W_GAMMA);
         Forward f = run_forward(c, g, p, d);
+        const int fwd_in = c->next_in;
         // (d) triple products and Gamma
         run_triple_gather(c, p, d, prec, f.St, o.dev);
         finish_out(c, o);
+        c->fwd = FwdCache{true, false, *g, *p, f, fwd_in};
     });
 }
 
@@ -832,10 +875,18 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         fill(p->tri_a, p->ta, d.na, inva, "tri_a");
         fill(p->tri_p, p->tp, d.np, invp, "tri_p");
 
+        // the forward tables: those of the previous call when the caller has
+        // enabled reuse and that call was a forward on the same grid and
+        // problem (its staged host inputs are kept: staging continues after
+        // them), else recomputed
+        const bool reuse = c->reuse_fwd && c->fwd.was_valid && same_inputs(c->fwd.g, *g) &&
+                           same_inputs(c->fwd.p, *p);
+        if (reuse) c->next_in = c->fwd.next_in;
         const double *dG = dev_in(c, dgamma, (size_t)ng);
         OutBuf oq = dev_out(c, dqk, dqk ? (size_t)d.np * d.nk : 0, W_DQ);
         OutBuf od = dev_out(c, ddelta, ddelta ? (size_t)d.L * d.nk : 0, W_DD);
-        Forward f = run_forward(c, g, p, d);
+        const Forward f = reuse ? c->fwd.f : run_forward(c, g, p, d);
+        const int fwd_in = reuse ? c->fwd.next_in : c->next_in;
         const int64_t ldz = (int64_t)d.nr * d.ldmu;
         const int64_t upad = pad_to(d.U, kRowPad);
 
@@ -924,6 +975,7 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         }
         finish_out(c, oq);
         finish_out(c, od);
+        c->fwd = FwdCache{true, false, *g, *p, f, fwd_in};
     });
 }
 

@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
             "modal_set_workspace_limit": [vp, sz],
             "modal_workspace_bytes": [vp, G, P, ctypes.c_int, ctypes.POINTER(sz)],
             "modal_enable_timing": [vp, ctypes.c_int],
+            "modal_set_forward_reuse": [vp, ctypes.c_int],
             "modal_stage_times": [vp, _dp, ctypes.c_int],
             "modal_gauss_legendre": [vp, i32, vp, vp],
             "modal_legendre_table": [vp, i32, i32, vp, vp],
@@ -100,7 +101,8 @@ def exported_symbols():
     """Names of the C entry points the binding declares."""
     return ["modal_create", "modal_destroy", "modal_set_stream", "modal_status_str",
             "modal_last_error", "modal_set_workspace_limit", "modal_workspace_bytes",
-            "modal_enable_timing", "modal_stage_times", "modal_gauss_legendre",
+            "modal_enable_timing", "modal_stage_times", "modal_set_forward_reuse",
+            "modal_gauss_legendre",
             "modal_legendre_table", "modal_sph_bessel_table", "modal_beta", "modal_S",
             "modal_gamma_from_S", "modal_gamma", "modal_gamma_backward"]
 
@@ -124,6 +126,7 @@ class Context:
         if not torch.cuda.is_available():
             raise ModalError(4, "no HIP device visible to torch")
         self.device = device
+        self.forward_reuse = False
         self.torch_device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.torch_device)
@@ -158,6 +161,13 @@ class Context:
 
     def enable_timing(self, on: bool = True):
         self.check(lib().modal_enable_timing(self.handle, int(on)))
+
+    def set_forward_reuse(self, on: bool = True):
+        """Let gamma_backward take the forward tables of the context's previous
+        gamma / gamma_backward call on the same projection instead of
+        recomputing them; the caller guarantees the inputs are unchanged."""
+        self.check(lib().modal_set_forward_reuse(self.handle, int(on)))
+        self.forward_reuse = bool(on)
 
     def stage_times(self) -> dict:
         ms = (ctypes.c_double * len(STAGES))()
@@ -245,6 +255,12 @@ class Projection:
     def nr(self) -> int:
         return self.r.numel()
 
+    def versions(self):
+        """In-place modification counters of every tensor the projection holds."""
+        return tuple(None if t is None else t._version
+                     for t in (self.k, self.wk, self.r, self.wr, self.delta, self.cl, self.qk, self.ql,
+                               self.tri_a, self.tri_p, self.mu, self.wmu))
+
     def structs(self):
         g = ModalGrid(self.lmin, self.lmax, self.k.numel(), _ptr(self.k), _ptr(self.wk),
                       self.r.numel(), _ptr(self.r), _ptr(self.wr), self.nmu, _ptr(self.mu),
@@ -317,13 +333,24 @@ class ModalProjectionFunction(torch.autograd.Function):
         p2 = dataclasses.replace(proj, qk=qk.detach().contiguous(), delta=delta.detach().contiguous())
         ctx.proj = p2
         ctx.precision = precision
-        return p2.gamma(precision)
+        out = p2.gamma(precision)
+        ctx.versions = p2.versions()
+        return out
 
     @staticmethod
     def backward(ctx, dgamma):
-        dq, dd = ctx.proj.gamma_backward(dgamma.contiguous(), ctx.precision,
-                                         want_q=ctx.needs_input_grad[0],
-                                         want_delta=ctx.needs_input_grad[1])
+        # the library may reuse this forward's tables only if no input has
+        # been modified in place since (it checks that no other call came
+        # between, and recomputes otherwise)
+        lc = ctx.proj.ctx
+        before = getattr(lc, "forward_reuse", False)
+        lc.set_forward_reuse(ctx.proj.versions() == ctx.versions)
+        try:
+            dq, dd = ctx.proj.gamma_backward(dgamma.contiguous(), ctx.precision,
+                                             want_q=ctx.needs_input_grad[0],
+                                             want_delta=ctx.needs_input_grad[1])
+        finally:
+            lc.set_forward_reuse(before)
         return dq, dd, None, None
 
 

@@ -141,6 +141,60 @@ def test_autograd_function(mp, ctx):
     np.testing.assert_allclose(_np(de.grad), _np(dd), rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_forward_reuse(mp, ctx, prec):
+    """modal_set_forward_reuse: a backward after a forward on the same inputs
+    takes the forward's tables and gives the recomputed gradient bit for bit;
+    after a forward on other inputs, or another entry point in between, it
+    recomputes (same result again)."""
+    cfg = synth.small_config(lmax=26, nk=60, nr=6, n1=4, kind="symmetric", seed_index=75)
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    other = mp.projection_from_inputs(ctx, synth.make_inputs(
+        synth.small_config(lmax=26, nk=60, nr=6, n1=4, kind="symmetric", seed_index=76)))
+    dG = ctx.to_dev(np.random.default_rng(5).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0])))
+    try:
+        ctx.set_forward_reuse(False)
+        pr.gamma(prec)
+        ref = [_np(t) for t in pr.gamma_backward(dG, prec)]
+        ctx.set_forward_reuse(True)
+        cases = {
+            "after its forward": lambda: pr.gamma(prec),
+            "after a forward on other inputs": lambda: (pr.gamma(prec), other.gamma(prec)),
+            "after another entry point": lambda: (pr.gamma(prec), other.beta()),
+            "after a backward": lambda: pr.gamma_backward(dG, prec),
+        }
+        for name, before in cases.items():
+            before()
+            got = [_np(t) for t in pr.gamma_backward(dG, prec)]
+            for g, r in zip(got, ref):
+                np.testing.assert_array_equal(g, r, err_msg=name)
+    finally:
+        ctx.set_forward_reuse(False)
+
+
+def test_autograd_reuse_follows_inplace_changes(mp, ctx):
+    """The autograd wrapper lets the library reuse the forward's tables only
+    while no input has been modified in place: after q is scaled in place the
+    gradient is that of the scaled q (recomputed), not the stale one."""
+    import torch
+    inp = synth.make_inputs(synth.small_config(lmax=24, nk=50, nr=5, n1=3, kind="symmetric"))
+    pr = mp.projection_from_inputs(ctx, inp)
+    W = ctx.to_dev(np.random.default_rng(3).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0])))
+    qk = pr.qk.clone().requires_grad_(True)
+    de = pr.delta.clone().requires_grad_(True)
+    G = mp.ModalProjectionFunction.apply(qk, de, pr, "fp64")
+    with torch.no_grad():
+        qk.mul_(1.5)
+    ((G * W) ** 2).sum().backward()
+    import dataclasses
+    p2 = dataclasses.replace(pr, qk=qk.detach().clone(), delta=de.detach().clone())
+    dq, dd = p2.gamma_backward(2 * G.detach() * W * W)
+    np.testing.assert_array_equal(_np(qk.grad), _np(dq))
+    np.testing.assert_array_equal(_np(de.grad), _np(dd))
+    assert ctx.forward_reuse is False
+
+
 def test_config4_finite_differences_and_mixed(mp, ctx):
     """lmax = 1000, 1540 x 1540 symmetric Gamma, L = Sum (Gamma * W)^2 with W
     a seeded N(0,1) matrix: 32 seeded entries of each gradient against
