@@ -30,7 +30,7 @@
 // the 16 pair tiles for the next step (its k rows read once for both) and
 // shares them through LDS (double-buffered, one barrier per step); loads its
 // A fragments straight from memory two steps ahead (two register sets); and
-// the first four waves stage the 32 source rows of the step after next.
+// all threads stage the 32 source rows of the step after next.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -139,19 +139,15 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
             al[i] = p[1];
         }
     };
-    // source rows: local 0..15 = j0.., 16..31 = k0..; 32 rows x 8 float4 =
-    // 256 float4, staged by the first four waves
-    const bool stager = t < 256;
-    const int srow = (t & 255) >> 3, sq = t & 7;
-    const uint32_t soff = ((uint32_t)(srow < BJ ? j0 + srow : k0 + srow - BJ) << 5) + 4 * sq;
+    // source rows: local 0..15 = j0.., 16..31 = k0..; 32 rows x 16 float2,
+    // one per thread (every thread, so that no branch leaves the compiler
+    // unable to count this wave's outstanding loads)
+    const int srow = t >> 4, sq = t & 15;
+    const uint32_t soff = ((uint32_t)(srow < BJ ? j0 + srow : k0 + srow - BJ) << 5) + 2 * sq;
     const size_t sstep = (size_t)A.upad << 5;
-    f4 sreg = f4{0.f, 0.f, 0.f, 0.f};
-    auto sload = [&](int64_t s) {
-        if (stager) sreg = *reinterpret_cast<const f4 *>(S32 + (size_t)s * sstep + soff);
-    };
-    auto sstore = [&](int buf) {
-        if (stager) *reinterpret_cast<f4 *>(&Src[buf][srow][4 * sq]) = sreg;
-    };
+    float2 sreg = make_float2(0.f, 0.f);
+    auto sload = [&](int64_t s) { sreg = *reinterpret_cast<const float2 *>(S32 + (size_t)s * sstep + soff); };
+    auto sstore = [&](int buf) { *reinterpret_cast<float2 *>(&Src[buf][srow][2 * sq]) = sreg; };
     // this wave generates pair tiles 2 wave and 2 wave + 1 (tile = j local);
     // the k values (this lane's k row, 8 z) are read once for both
     f4 k0v, k1v;
