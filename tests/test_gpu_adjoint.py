@@ -173,6 +173,38 @@ def test_forward_reuse(mp, ctx, prec):
         ctx.set_forward_reuse(False)
 
 
+def test_forward_reuse_host_inputs(mp, ctx):
+    """Reuse with every input in host memory: the forward's staged copies of
+    the inputs stay in place while the backward stages dL/dGamma after them
+    (the result equals the device-input backward bit for bit)."""
+    import ctypes
+    cfg = synth.small_config(lmax=22, nk=48, nr=5, n1=3, kind="ordered", seed_index=77)
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    dG = np.random.default_rng(6).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    ref = [_np(t) for t in pr.gamma_backward(ctx.to_dev(dG))]
+    host = {name: np.ascontiguousarray(_np(getattr(pr, name))) for name in
+            ("k", "wk", "r", "wr", "delta", "cl", "qk", "ql", "tri_a", "tri_p")}
+    hp = lambda a: a.ctypes.data
+    g = mp.ModalGrid(pr.lmin, pr.lmax, host["k"].size, hp(host["k"]), hp(host["wk"]), host["r"].size,
+                     hp(host["r"]), hp(host["wr"]), pr.nmu, None, None, 0)
+    p = mp.ModalProblem(hp(host["delta"]), hp(host["cl"]), pr.np_, hp(host["qk"]), pr.na, hp(host["ql"]),
+                        pr.v_power, 0, host["tri_a"].shape[0], hp(host["tri_a"]), host["tri_p"].shape[0],
+                        hp(host["tri_p"]))
+    gamma = np.zeros((host["tri_a"].shape[0], host["tri_p"].shape[0]))
+    dq = np.zeros(host["qk"].shape)
+    dd = np.zeros(host["delta"].shape)
+    try:
+        ctx.set_forward_reuse(True)
+        ctx.check(mp.lib().modal_gamma(ctx.handle, ctypes.byref(g), ctypes.byref(p), 0, gamma.ctypes.data))
+        ctx.check(mp.lib().modal_gamma_backward(ctx.handle, ctypes.byref(g), ctypes.byref(p), 0,
+                                                dG.ctypes.data, dq.ctypes.data, dd.ctypes.data))
+    finally:
+        ctx.set_forward_reuse(False)
+    np.testing.assert_array_equal(dq, ref[0])
+    np.testing.assert_array_equal(dd, ref[1])
+
+
 def test_autograd_reuse_follows_inplace_changes(mp, ctx):
     """The autograd wrapper lets the library reuse the forward's tables only
     while no input has been modified in place: after q is scaled in place the
