@@ -69,7 +69,7 @@ def algorithmic_flops(cfg) -> dict:
 
 
 KERNEL_SOURCES = {"k_adj_fac": "k_adjoint_fac.hip", "k_triple_bt": "k_triple_mx.hip",
-                  "k_adj_f64": "k_adjoint_f64.hip", "k_triple_f64": "k_triple.hip"}
+                  "k_adj_fac64": "k_adjoint_fac64.hip", "k_triple_f64": "k_triple.hip"}
 
 
 def measured_traffic(kernel: str, tag: str):
@@ -286,7 +286,7 @@ def main() -> int:
                 "kernel": kernel, "flops_per_launch": flops[stage], "mean_launch_ms": ms}
 
     kfwd = "k_triple_bt" if main_prec == "mixed" else "k_triple_f64"
-    kadj = "k_adj_fac" if main_prec == "mixed" else "k_adj_f64"
+    kadj = "k_adj_fac" if main_prec == "mixed" else "k_adj_fac64"
     r_fwd = roof(kfwd, "triple", main["stage_ms_forward"]["triple"])
     r_adj = roof(kadj, "adj_triple", main["stage_ms_adjoint"]["adj_triple"]) if adjoint else None
     dominant = r_adj if adjoint and r_adj["mean_launch_ms"] > r_fwd["mean_launch_ms"] else r_fwd

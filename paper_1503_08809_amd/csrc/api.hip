@@ -20,7 +20,7 @@ thread_local std::string g_last_error;   // for calls without a usable context
 enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
     W_S32, W_SH, W_SL, W_GAMMA,
-    W_INVA, W_INVP, W_H, W_SHAT, W_PBL, W_BHAT, W_AHAT, W_DQ, W_DD,
+    W_INVA, W_INVP, W_H, W_SHAT, W_BHAT, W_AHAT, W_DQ, W_DD,
     W_IN0, NSLOTS = W_IN0 + 16
 };
 
@@ -897,15 +897,6 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
               "H2D");
         hipck(c, hipMemcpyAsync(dinvp, invp.data(), sizeof(int) * invp.size(), hipMemcpyHostToDevice, c->stream),
               "H2D");
-        // pair blocks (v block <= w block) of 16 rows
-        const int nvb = (d.U + 15) / 16;
-        std::vector<int2> pbl;
-        for (int vb = 0; vb < nvb; ++vb)
-            for (int wb = vb; wb < nvb; ++wb) pbl.push_back(make_int2(vb, wb));
-        const int npb = (int)pbl.size();
-        int2 *dpb = (int2 *)ws_get(c, W_PBL, sizeof(int2) * pbl.size());
-        hipck(c, hipMemcpyAsync(dpb, pbl.data(), sizeof(int2) * pbl.size(), hipMemcpyHostToDevice, c->stream),
-              "H2D");
         // z blocks of the output: whole z tiles of the kernel (St is zero past ldz)
         const int64_t nzb = ldz / 32, nzbp = (nzb + kZBlockPad - 1) / kZBlockPad * kZBlockPad;
         double *Shat = (double *)ws_get(c, W_SHAT, sizeof(double) * (size_t)nzbp * upad * 32);
@@ -922,16 +913,16 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
             hipck(c, launch_adj_fac(d.U, upad, nzbp, f.St, sb, Hc, Shat, c->stream), "dL/dS");
         } else {
-            const int nib = (int)(upad / adj_rowblock());
-            double *Hc = (double *)ws_get(c, W_H, sizeof(double) * (size_t)npb * nib * 32768);
+            const int nib = (int)(upad / adj_fac64_rowblock()), nws = (d.U + 15) / 16;
+            double *Hc = (double *)ws_get(c, W_H, sizeof(double) * (size_t)v_step_offset16(d.U, nws) * nib * 2048);
             {
                 StageTimer tm(c, MODAL_STAGE_ADJ_PREP);
-                hipck(c, launch_build_hc_f64(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, dpb, npb, nib, Hc,
-                                             c->stream),
+                hipck(c, launch_build_hc_fac64(p->kind, d.U, d.np, d.na, dinva, dinvp, dG, p->tp, nib, Hc,
+                                               c->stream),
                       "build Hc");
             }
             StageTimer tm(c, MODAL_STAGE_ADJ_TRIPLE);
-            hipck(c, launch_adj_triple_f64(dpb, npb, d.U, upad, nzbp, f.St, Hc, Shat, c->stream), "dL/dS");
+            hipck(c, launch_adj_fac64(d.U, upad, nzbp, f.St, Hc, Shat, c->stream), "dL/dS");
         }
         // (c) adjoint
         double *bhat = (double *)ws_get(c, W_BHAT, sizeof(double) * (size_t)d.np * d.L * d.nr);

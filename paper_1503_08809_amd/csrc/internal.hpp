@@ -133,16 +133,8 @@ hipError_t launch_split_bf16(int64_t n, const double *St, float *S32, uint16_t *
 
 // Adjoint stages (k_adjoint*.hip).  Step d: dL/dSt_u(z) = Sum_{v <= w}
 // Hc[u][(v,w)] St_v(z) St_w(z), Hc built from G in each kernel's operand
-// order.  FP64 (k_adjoint_f64.hip): over pair blocks pblocks[npb] (16-row v
-// block <= w block) and nib row blocks of adj_rowblock() rows.  Shat and St
-// are z-blocked with nzb z blocks (a multiple of kZBlockPad, zero past the
-// data); rows >= U of Shat are left unwritten.
-int adj_rowblock();            // FP64 kernel (Hc: 32768 doubles per pair block and row block)
-hipError_t launch_build_hc_f64(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
-                               const double *G, int tp, const int2 *pblocks, int npb, int nib, double *Hc,
-                               hipStream_t s);
-hipError_t launch_adj_triple_f64(const int2 *pblocks, int npb, int U, int64_t upad, int64_t nzb,
-                                 const double *St, const double *Hc, double *Shat, hipStream_t s);
+// order.  Shat and St are z-blocked with nzb z blocks (a multiple of
+// kZBlockPad, zero past the data); rows >= U of Shat are left unwritten.
 // Factored mixed adjoint of step d (k_adjoint_fac.hip): for every v, the w
 // steps (32 wide) from the one holding v to the last; Hc is stored per
 // (v, w step) as [v_step_offset(v) + ws - v / 32][row block of 256][row
@@ -154,6 +146,19 @@ __host__ __device__ inline int64_t v_step_offset(int v, int nws)
     return 32 * (a * nws - a * (a - 1) / 2) + b * (nws - a);
 }
 int adj_fac_rowblock();
+// FP64 factored adjoint of step d (k_adjoint_fac64.hip): the same order with
+// 16-wide w steps; Hc in FP64 per (v, w step) as [step][row block of 128]
+// [k step 4][row tile 8][lane] (2048 doubles per step and row block).
+__host__ __device__ inline int64_t v_step_offset16(int v, int nws)
+{
+    const int64_t a = v >> 4, b = v & 15;      // Sum_{v' < v} (nws - v' / 16)
+    return 16 * (a * nws - a * (a - 1) / 2) + b * (nws - a);
+}
+int adj_fac64_rowblock();
+hipError_t launch_build_hc_fac64(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                                 const double *G, int tp, int nib, double *Hc, hipStream_t s);
+hipError_t launch_adj_fac64(int U, int64_t upad, int64_t nzb, const double *St, const double *Hc, double *Shat,
+                            hipStream_t s);
 hipError_t launch_build_hc_fac(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
                                const double *G, int tp, int nib, uint4 *Hc, hipStream_t s);
 hipError_t launch_split_b(int64_t nzb, int U, int64_t upad, const double *St, uint4 *SB, hipStream_t s);

@@ -9,7 +9,7 @@
 //     dL/dSt_u(z) = 3 Sum_{v,w} H[u,v,w] St_v(z) St_w(z).
 // Here H is evaluated entry by entry from G (each entry gathers the Gamma
 // entries it feeds; no atomics) straight into the operand order of the
-// kernels (k_adjoint_f64.hip, k_adjoint_fac.hip) as
+// kernels (k_adjoint_fac64.hip, k_adjoint_fac.hip) as
 // Hc[u][(v,w)] = 3 c_vw H[u,v,w] over pairs v <= w, and dL/dS = W^(1/3) dL/dSt.
 // Step c.  betahat_p(l, r) = Sum_{a, mu} [w_l qbar_a(l) P_l(mu)] Shat_ap(r, mu):
 //   per p and per parity of l, one GEMM with the (a, mu >= 0) depth, a
@@ -122,28 +122,26 @@ __global__ void k_build_hc_fac(int kind, int U, int np, int na, const int *__res
     o[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
 }
 
-// The same Hc in FP64, in the order of the FP64 adjoint kernel:
-// Hc[pair block][row block of 128][v local][step][row tile][lane], a lane
-// holding row 16-tile + lane % 16 and pair (v local, 4 step + lane / 16).
-__global__ void k_build_hc_f64(int kind, int U, int np, int na, const int *__restrict__ inv_a,
-                               const int *__restrict__ inv_p, const double *__restrict__ G, int tp,
-                               const int2 *__restrict__ pblocks, int npb, int nib, double *__restrict__ Hc)
+// The same Hc in FP64 for the FP64 factored kernel: per v, the 16-wide w
+// steps from the one holding v to the last ([v_step_offset16(v) + ws'][row
+// block of 128][k step 4][row tile 8][lane], lane: row 16 tile + lane % 16,
+// w = 16 ws + 4 k + lane / 16); entries with w < v are zero.  blockIdx.y = v.
+__global__ void k_build_hc_fac64(int kind, int U, int np, int na, const int *__restrict__ inv_a,
+                                 const int *__restrict__ inv_p, const double *__restrict__ G, int tp, int nws,
+                                 int nib, double *__restrict__ Hc)
 {
-    const int64_t n = (int64_t)npb * nib * 16 * 4 * 8 * 64;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int lane = (int)(e & 63), rt = (int)((e >> 6) & 7), kk = (int)((e >> 9) & 3);
-        const int sv = (int)((e >> 11) & 15);
-        const int64_t pbib = e >> 15;
-        const int ib = (int)(pbib % nib), pb = (int)(pbib / nib);
-        const int2 b = pblocks[pb];
-        const int u = ib * 128 + rt * 16 + (lane & 15);
-        const int v = b.x * 16 + sv, w = b.y * 16 + 4 * kk + (lane >> 4);
-        double h = 0.0;
-        if (u < U && v < U && w < U && v <= w)
-            h = (v < w ? 6.0 : 3.0) * adj_h(kind, np, na, inv_a, inv_p, G, tp, u, v, w);
-        Hc[e] = h;
-    }
+    const int v = blockIdx.y;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(e & 63), rt = (int)((e >> 6) & 7), k = (int)((e >> 9) & 3);
+    const int64_t r = e >> 11;
+    const int ib = (int)(r % nib), wsr = (int)(r / nib);
+    const int ws = (v >> 4) + wsr;
+    if (ws >= nws) return;
+    const int u = ib * 128 + rt * 16 + (lane & 15);
+    const int w = 16 * ws + 4 * k + (lane >> 4);
+    double h = 0.0;
+    if (u < U && w < U && w >= v) h = (w > v ? 6.0 : 3.0) * adj_h(kind, np, na, inv_a, inv_p, G, tp, u, v, w);
+    Hc[((size_t)(v_step_offset16(v, nws) + wsr) * nib + ib) * 2048 + (k * 8 + rt) * 64 + lane] = h;
 }
 
 // ---- betahat ------------------------------------------------------------------
@@ -282,15 +280,15 @@ hipError_t launch_build_hc_fac(int kind, int U, int np, int na, const int *inv_a
     return hipGetLastError();
 }
 
-hipError_t launch_build_hc_f64(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
-                               const double *G, int tp, const int2 *pblocks, int npb, int nib, double *Hc,
-                               hipStream_t s)
+hipError_t launch_build_hc_fac64(int kind, int U, int np, int na, const int *inv_a, const int *inv_p,
+                                 const double *G, int tp, int nib, double *Hc, hipStream_t s)
 {
-    const int64_t n = (int64_t)npb * nib * 16 * 4 * 8 * 64;
-    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1 << 20);
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_hc_f64, dim3((unsigned)blocks), dim3(256), 0, s, kind, U, np, na, inv_a, inv_p,
-                       G, tp, pblocks, npb, nib, Hc);
+    const int nws = (U + 15) / 16;
+    const int64_t n = (int64_t)nws * nib * 2048;
+    if (U > 65535) return hipErrorInvalidValue;     // grid y limit
+    if ((n + 255) / 256 > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_build_hc_fac64, dim3((unsigned)((n + 255) / 256), (unsigned)U), dim3(256), 0, s, kind, U,
+                       np, na, inv_a, inv_p, G, tp, nws, nib, Hc);
     return hipGetLastError();
 }
 
