@@ -124,24 +124,26 @@ __global__ void k_build_hc_fac(int kind, int U, int np, int na, const int *__res
 
 // The same Hc in FP64 for the FP64 factored kernel: per v, the 16-wide w
 // steps from the one holding v to the last ([v_step_offset16(v) + ws'][row
-// block of 128][k step 4][row tile 8][lane], lane: row 16 tile + lane % 16,
-// w = 16 ws + 4 k + lane / 16); entries with w < v are zero.  blockIdx.y = v.
+// block of 128][row tile 8][k pair 2][lane][2]; lane: row 16 tile + lane % 16,
+// w = 16 ws + 4 k + lane / 16 with k = 2 (k pair) + the last index), so that
+// one row tile is 2 KB in a row and a lane's two k of one pair are adjacent;
+// entries with w < v are zero.  blockIdx.y = v.
 __global__ void k_build_hc_fac64(int kind, int U, int np, int na, const int *__restrict__ inv_a,
                                  const int *__restrict__ inv_p, const double *__restrict__ G, int tp, int nws,
                                  int nib, double *__restrict__ Hc)
 {
     const int v = blockIdx.y;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = (int)(e & 63), rt = (int)((e >> 6) & 7), k = (int)((e >> 9) & 3);
+    const int el = (int)(e & 1), lane = (int)((e >> 1) & 63), kp = (int)((e >> 7) & 1), rt = (int)((e >> 8) & 7);
     const int64_t r = e >> 11;
     const int ib = (int)(r % nib), wsr = (int)(r / nib);
     const int ws = (v >> 4) + wsr;
     if (ws >= nws) return;
     const int u = ib * 128 + rt * 16 + (lane & 15);
-    const int w = 16 * ws + 4 * k + (lane >> 4);
+    const int w = 16 * ws + 4 * (2 * kp + el) + (lane >> 4);
     double h = 0.0;
     if (u < U && w < U && w >= v) h = (w > v ? 6.0 : 3.0) * adj_h(kind, np, na, inv_a, inv_p, G, tp, u, v, w);
-    Hc[((size_t)(v_step_offset16(v, nws) + wsr) * nib + ib) * 2048 + (k * 8 + rt) * 64 + lane] = h;
+    Hc[((size_t)(v_step_offset16(v, nws) + wsr) * nib + ib) * 2048 + (e & 2047)] = h;
 }
 
 // ---- betahat ------------------------------------------------------------------

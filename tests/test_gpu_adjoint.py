@@ -76,6 +76,28 @@ def test_backward_mixed_vs_oracle(mp, ctx, oracle, kind, n1, lmax, nr, nk):
     assert eq <= 1e-4 and ed <= 1e-4
 
 
+# U = n1^2 rows against the adjoint kernels' row blocks (FP64: 128 rows,
+# mixed: 256), with 16-row tiles: U below one block (81: six live tiles),
+# exact multiples (256), a last block of one (144, 900 - 7 * 128 = 4 rows
+# likewise), seven (225), eight (121: handled as a full block) and nine (400,
+# mixed) live tiles; nr = 10 gives several z tiles and a ragged last one.
+@pytest.mark.parametrize("prec,n1", [
+    ("fp64", 9), ("fp64", 11), ("fp64", 12), ("fp64", 15), ("fp64", 16),
+    ("mixed", 12), ("mixed", 17), ("mixed", 20),
+])
+def test_backward_row_tails_vs_oracle(mp, ctx, oracle, prec, n1):
+    cfg = synth.small_config(lmax=14, nk=30, nr=10, n1=n1, kind="symmetric", seed_index=80 + n1)
+    inp = synth.make_inputs(cfg)
+    dG = np.random.default_rng(n1).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    pr = mp.projection_from_inputs(ctx, inp)
+    dq, dd = pr.gamma_backward(ctx.to_dev(dG), prec)
+    rq, rd = oracle.gamma_full_backward(inp, dG)
+    eq, ed = normwise(_np(dq), rq), normwise(_np(dd), rd)
+    print(f"{prec} adjoint U={n1 * n1}: dq {eq:.2e}, ddelta {ed:.2e}")
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert eq <= tol and ed <= tol
+
+
 def test_backward_mixed_config2_vs_fp64(mp, ctx):
     """lmax = 500, U = 256 ordered: the mixed adjoint against the FP64 one."""
     inp = synth.make_inputs(synth.CONFIGS[2])
