@@ -279,6 +279,9 @@ __global__ __launch_bounds__(512) void k_adj_fac(FacArgs A, const double *__rest
         if (!step(std::integral_constant<int, 1>())) break;
         if (!step(std::integral_constant<int, 2>())) break;
     }
+    // no copy into this workgroup's LDS may outlive it (the last steps issue
+    // copies that no step reads)
+    __builtin_amdgcn_s_waitcnt(0x0f70);                                 // vmcnt(0)
 }
 
 // St pre-split in the B-operand order of the 16x16x32 BF16 matrix-core step:
