@@ -368,6 +368,9 @@ hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group
         for (int tt = gt0[g]; tt < gt0[g + 1]; ++tt) mj = std::max(mj, maxj[tt]);
         for (int rb = 0; rb <= mj / rowblock; ++rb) tasks.push_back(make_int2(g, rb));
     }
+    // row block major: the workgroups co-resident on one XCD (contiguous task
+    // runs) share their 128 A rows, and neighbouring groups part of their rows
+    std::stable_sort(tasks.begin(), tasks.end(), [](int2 a, int2 b) { return a.y < b.y; });
     plan.ntasks = (int)tasks.size();
 
     hipError_t e = hipSuccess;
