@@ -8,7 +8,10 @@ ABI) and to the oracle, and compares element by element.  Tolerances:
   test (1e-13 .. 1e-11 relative to the largest value);
 * Gamma from the FP64 path: normwise error max|G - G_ref| / max|G_ref| at
   most 1e-6 (the FP64 bar), and elementwise within 1e-9 of max|G_ref|;
-* Gamma from the mixed path: normwise at most 1e-4 (the mixed bar).
+* Gamma from the mixed path: normwise at most 1e-4 (the mixed bar);
+* at the large workloads (stored oracle entries), the entries with
+  |G_ref| >= 1e-3 max|G| also elementwise: FP64 within 1e-9 of |G_ref| (two
+  FP64 sums that differ in order only), mixed within 1e-4 of |G_ref|.
 """
 import numpy as np
 import pytest
@@ -335,6 +338,44 @@ def _golden_samples(cfg):
     return a[:, 0].astype(np.int64), a[:, 1].astype(np.int64), a[:, 2]
 
 
+def _large_entries(g, rows, cols, ref, scale, floor=1e-3):
+    """(number of stored entries with |ref| >= floor * scale, their largest
+    elementwise relative error): the secondary error metric, on the entries
+    large enough for it to be well posed."""
+    big = np.abs(ref) >= floor * scale
+    if not big.any():
+        return 0, 0.0
+    rel = np.abs(g[rows, cols] - ref)[big] / np.abs(ref[big])
+    return int(big.sum()), float(rel.max())
+
+
+# elementwise bars on the large stored entries: two FP64 sums that differ in
+# order only; the mixed path's bar as normwise
+FP64_ELEM_BAR = 1e-9
+
+
+def test_gamma_config4_sampled(mp, ctx):
+    """lmax = 1000, 1540 x 1540 symmetric Gamma: both paths against stored
+    oracle entries, and the mixed path against the FP64 path."""
+    cfg = synth.CONFIGS[4]
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    g64 = _np(pr.gamma("fp64"))
+    gm = _np(pr.gamma("mixed"))
+    assert g64.shape == (1540, 1540) and np.all(np.isfinite(g64))
+    rows, cols, ref = _golden_samples(cfg)
+    scale = np.abs(g64).max()
+    e64 = np.abs(g64[rows, cols] - ref).max() / scale
+    em = np.abs(gm[rows, cols] - ref).max() / scale
+    ew = normwise(gm, g64)
+    n64, r64 = _large_entries(g64, rows, cols, ref, scale)
+    nm, rm = _large_entries(gm, rows, cols, ref, scale)
+    print(f"lmax=1000: FP64 vs oracle {e64:.2e}, mixed vs oracle {em:.2e}, mixed vs FP64 {ew:.2e}; "
+          f"{n64} large entries: FP64 {r64:.2e}, mixed {rm:.2e} elementwise")
+    assert e64 <= FP64_BAR and em <= MIXED_BAR and ew <= MIXED_BAR
+    assert n64 >= 1 and r64 <= FP64_ELEM_BAR and rm <= MIXED_BAR
+
+
 def test_gamma_config3_sampled(mp, ctx):
     """lmax = 2500, 4960 x 4960 symmetric Gamma: both paths against stored
     oracle entries, and the mixed path against the FP64 path."""
@@ -349,8 +390,12 @@ def test_gamma_config3_sampled(mp, ctx):
     e64 = np.abs(g64[rows, cols] - ref).max() / scale
     em = np.abs(gm[rows, cols] - ref).max() / scale
     ew = normwise(gm, g64)
-    print(f"lmax=2500: FP64 vs oracle {e64:.2e}, mixed vs oracle {em:.2e}, mixed vs FP64 {ew:.2e}")
+    n64, r64 = _large_entries(g64, rows, cols, ref, scale)
+    nm, rm = _large_entries(gm, rows, cols, ref, scale)
+    print(f"lmax=2500: FP64 vs oracle {e64:.2e}, mixed vs oracle {em:.2e}, mixed vs FP64 {ew:.2e}; "
+          f"{n64} large entries: FP64 {r64:.2e}, mixed {rm:.2e} elementwise")
     assert e64 <= FP64_BAR and em <= MIXED_BAR and ew <= MIXED_BAR
+    assert n64 >= 1 and r64 <= FP64_ELEM_BAR and rm <= MIXED_BAR
 
 
 @pytest.fixture(scope="module")
@@ -367,6 +412,9 @@ def test_gamma_config5_mixed_sampled(mp, ctx, config5):
     gm = _np(pr.gamma("mixed"))
     assert gm.shape == (11480, 11480) and np.all(np.isfinite(gm))
     rows, cols, ref = _golden_samples(cfg)
-    em = np.abs(gm[rows, cols] - ref).max() / np.abs(gm).max()
-    print(f"lmax=4000: mixed vs oracle {em:.2e}")
+    scale = np.abs(gm).max()
+    em = np.abs(gm[rows, cols] - ref).max() / scale
+    nm, rm = _large_entries(gm, rows, cols, ref, scale)
+    print(f"lmax=4000: mixed vs oracle {em:.2e}; {nm} large entries: mixed {rm:.2e} elementwise")
     assert em <= MIXED_BAR
+    assert nm >= 1 and rm <= MIXED_BAR
