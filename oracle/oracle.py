@@ -348,3 +348,90 @@ def brute_force_gamma_ordered(inp, beta_arr=None) -> np.ndarray:
     ta, tp = inp.tri_a, inp.tri_p
     return G[ta[:, 0][:, None], tp[:, 0][None, :], ta[:, 1][:, None], tp[:, 1][None, :],
              ta[:, 2][:, None], tp[:, 2][None, :]]
+
+
+# ---------------------------------------------------------------- the full Gamma
+# Gamma = <Q, Q>^-1 <Q, Q~> (Appendix): the late-time Gram matrix <Q_n, Q_m>
+# is the inner product of Sec. 2.1 between two late-time modes.  With h^2 as
+# the Gauss-Legendre mu integral (Sec. 2.2) it separates like Eq. (2D), with
+# G_ab(mu) = Sum_l (2l+1) / v_l^2 qbar_a(l) qbar_b(l) P_l(mu) in place of
+# P_ii'(r, mu) and no r integral.
+
+
+def gram_G(inp, mu) -> np.ndarray:
+    """G[a][b][j] = Sum_l (2l+1)^(1 - 2 v_power) qbar_a(l) qbar_b(l) P_l(mu_j)."""
+    c = inp.cfg
+    P = legendre_table(c.lmax, mu)[:, c.lmin:]                      # [mu][l - lmin]
+    l = inp.ells.astype(np.float64)
+    W = (2 * l + 1) ** (1.0 - 2.0 * c.v_power)
+    return np.einsum("l,al,bl,jl->abj", W, inp.ql, inp.ql, P)
+
+
+def gram_entries(inp, rows, cols, mu=None, wmu=None) -> np.ndarray:
+    """<Q_n, Q_m> for n = tri_a[rows[e]], m = tri_a[cols[e]]: the mu sum of
+    the product (ordered lists, constant 1/(8 pi)) or of the permanent of the
+    3x3 block G[n_s][m_t] (symmetric lists, 1/(48 pi))."""
+    c = inp.cfg
+    if mu is None:
+        mu, wmu = gauss_legendre(c.nmu)
+    G = gram_G(inp, mu)
+    ta = inp.tri_a
+    out = np.empty(len(rows))
+    for e, (n, m) in enumerate(zip(rows, cols)):
+        a, b = ta[n], ta[m]
+        M = [[G[a[s], b[t]] for t in range(3)] for s in range(3)]
+        if c.kind == "ordered":
+            f = M[0][0] * M[1][1] * M[2][2]
+            out[e] = (wmu * f).sum() / (8.0 * math.pi)
+        else:
+            f = np.zeros_like(wmu)
+            for sg in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+                f = f + M[0][sg[0]] * M[1][sg[1]] * M[2][sg[2]]
+            out[e] = (wmu * f).sum() / (48.0 * math.pi)
+    return out
+
+
+def gram_full(inp, mu=None, wmu=None) -> np.ndarray:
+    """The whole Gram matrix [ta][ta] (small workloads only)."""
+    n = inp.tri_a.shape[0]
+    rows, cols = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return gram_entries(inp, rows.ravel(), cols.ravel(), mu, wmu).reshape(n, n)
+
+
+def gamma_modal(inp) -> np.ndarray:
+    """Gamma = <Q, Q>^-1 Gamma' (Gamma' = gamma_full), a dense linear solve."""
+    return np.linalg.solve(gram_full(inp), gamma_full(inp))
+
+
+def brute_force_gram_ordered(inp) -> np.ndarray:
+    """Ordered Gram matrix straight from the inner product of Sec. 2.1 with
+    the exact Wigner symbol: Sum over every ordered (l1, l2, l3) of
+
+        2 (l1 l2 l3; 000)^2 / (8 pi) * prod_s (2 l_s + 1)^(1 - 2 v_power)
+            * prod_s qbar_{a_s}(l_s) qbar_{b_s}(l_s)
+
+    (h^2 / (v1 v2 v3)^2 with h^2 = prod(2l+1)/(4 pi) (3j)^2).  No Legendre
+    polynomials and no mu quadrature appear."""
+    c = inp.cfg
+    L = c.L
+    C = np.zeros((L, L, L))
+    cache = {}
+    for i1 in range(L):
+        for i2 in range(L):
+            for i3 in range(L):
+                key = tuple(sorted((i1 + c.lmin, i2 + c.lmin, i3 + c.lmin)))
+                if key not in cache:
+                    cache[key] = threej000_sq(*key)
+                C[i1, i2, i3] = cache[key]
+    l = inp.ells.astype(np.float64)
+    W = (2 * l + 1) ** (1.0 - 2.0 * c.v_power)
+    C *= 2.0 / (8.0 * math.pi) * W[:, None, None] * W[None, :, None] * W[None, None, :]
+    na = inp.ql.shape[0]
+    U = inp.ql.T[:, :, None] * inp.ql.T[:, None, :]                  # [l][a][b]
+    T1 = np.tensordot(C, U, axes=([2], [0]))                         # [l1][l2][a3][b3]
+    T2 = np.tensordot(T1, U, axes=([1], [0]))                        # [l1][a3][b3][a2][b2]
+    T3 = np.tensordot(U, T2, axes=([0], [0]))                        # [a1][b1][a3][b3][a2][b2]
+    G = T3.transpose(0, 1, 4, 5, 2, 3)
+    ta = inp.tri_a
+    return G[ta[:, 0][:, None], ta[:, 0][None, :], ta[:, 1][:, None], ta[:, 1][None, :],
+             ta[:, 2][:, None], ta[:, 2][None, :]]
