@@ -216,6 +216,31 @@ modal_status modal_gamma_from_S(modal_ctx ctx, const modal_grid *grid,
 modal_status modal_gamma(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
                          modal_precision prec, double *gamma);
 
+/* The late-time Gram matrix <Q_n, Q_m> of the inner product of Sec. 2.1
+ * (weights h^2 / (v1 v2 v3)^2), between the late-time modes of tri_a and
+ * themselves: gram [ta][ta], symmetric.  With h^2 as the Gauss-Legendre mu
+ * integral (Sec. 2.2) it takes the form of Eq. (2D) with
+ * G_ab(mu) = Sum_l (2l+1) / v_l^2 qbar_a(l) qbar_b(l) P_l(mu) in place of
+ * P_ii'(r, mu) and no r integral; the same kernels compute it.  Reads the l
+ * range, nmu (and mu, wmu if given) of the grid, and na, ql, v_power, kind,
+ * ta and tri_a of the problem (cl, np, qk, delta and tri_p are not used, but
+ * cl must be valid).  na * na <= 8192.  Precision as for modal_gamma. */
+modal_status modal_gram(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
+                        modal_precision prec, double *gram);
+
+/* The full projection matrix Gamma = <Q, Q>^-1 <Q, Q~> (Appendix):
+ * gamma [ta][tp] = gram^-1 Gamma', with Gamma' as modal_gamma computes it in
+ * the given precision and gram = <Q, Q> over tri_a (modal_gram) in FP64,
+ * solved by a Cholesky factorisation (rocSOLVER) and two triangular solves
+ * (rocBLAS).  MODAL_ERR_NUMERIC if the Gram matrix is not positive definite
+ * in FP64: late-time modes that are linearly dependent, or so nearly so that
+ * rounding makes a pivot non-positive (products of polynomials in l of total
+ * degree above about 25, restricted to the triangle condition, reach that at
+ * lmax in the thousands).  The result's rounding grows with the condition
+ * number of <Q, Q>.  The workspace holds gram besides the forward's. */
+modal_status modal_gamma_modal(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
+                               modal_precision prec, double *gamma);
+
 /* Gradient of a scalar loss L of Gamma (the adjoint of modal_gamma, with the
  * same grid and problem): given dgamma = dL/dGamma ([ta][tp]), writes
  * dqk = dL/dq_p(k) ([np][nk]) and ddelta = dL/dDelta_l(k) ([L][nk]); either

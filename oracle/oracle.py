@@ -364,7 +364,8 @@ def gram_G(inp, mu) -> np.ndarray:
     P = legendre_table(c.lmax, mu)[:, c.lmin:]                      # [mu][l - lmin]
     l = inp.ells.astype(np.float64)
     W = (2 * l + 1) ** (1.0 - 2.0 * c.v_power)
-    return np.einsum("l,al,bl,jl->abj", W, inp.ql, inp.ql, P)
+    # for each a, a product over l of the rows W qbar_a qbar_b with the P table
+    return np.stack([(inp.ql * (W * inp.ql[a])) @ P.T for a in range(inp.ql.shape[0])])
 
 
 def gram_entries(inp, rows, cols, mu=None, wmu=None) -> np.ndarray:

@@ -4,6 +4,9 @@
 // the boundary: every entry point returns a modal_status.
 #include "internal.hpp"
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -20,7 +23,7 @@ thread_local std::string g_last_error;   // for calls without a usable context
 enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
     W_S32, W_SH, W_SL, W_GAMMA,
-    W_INVA, W_INVP, W_H, W_SHAT, W_BHAT, W_AHAT, W_DQ, W_DD,
+    W_INVA, W_INVP, W_H, W_SHAT, W_BHAT, W_AHAT, W_DQ, W_DD, W_GRAM, W_INFO,
     W_IN0, NSLOTS = W_IN0 + 16
 };
 
@@ -81,6 +84,7 @@ struct modal_ctx_s {
     bool timing = false;
     bool reuse_fwd = false;            // modal_set_forward_reuse
     FwdCache fwd;
+    rocblas_handle blas = nullptr;     // for the solve of the full Gamma (created on first use)
     // per stage: a pool of (start, end) event pairs; the first `used` belong
     // to the last call (chunked stages record one pair per chunk)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MODAL_NSTAGES];
@@ -546,6 +550,81 @@ void run_triple_gather(modal_ctx c, const modal_problem *p, const Dims &d, modal
     hipck(c, launch_gather_bt(p->kind, p->ta, p->tp, ta, tp, d.np, plan, T, gamma, c->stream), "gather");
 }
 
+// The late-time Gram matrix <Q_n, Q_m> over tri_a x tri_a (Appendix; the
+// inner product of Sec. 2.1 with h^2 as the mu integral of Sec. 2.2): the
+// same l contraction and triple products as Eq. (2D), with qbar_b(l) in place
+// of beta_p(l, r), weights (2l+1) / v_l^2 (no C_l) and one radial point of
+// unit weight (no r integral).  The qbar table [na][L] is the beta layout
+// [np][L][nr] for np = na, nr = 1.
+void run_gram(modal_ctx c, const modal_grid *g, const modal_problem *p, const Dims &d, modal_precision prec,
+              double *gram)
+{
+    static const double one = 1.0;
+    Dims dg = d;
+    dg.nr = 1;
+    dg.np = d.na;
+    dg.U = d.na * d.na;
+    const Grid G = stage_grid(c, g, d);
+    const double *ql = dev_in(c, p->ql, (size_t)d.na * d.L);
+    const double *r1 = dev_in(c, &one, 1), *wr1 = dev_in(c, &one, 1);
+    double *P = (double *)ws_get(c, W_P, sizeof(double) * (size_t)d.L * d.ldmu);
+    double *wl = (double *)ws_get(c, W_WL, sizeof(double) * d.L);
+    const int64_t ldz = dg.ldmu;
+    double *wz = (double *)ws_get(c, W_WZ, sizeof(double) * ldz);
+    const int Upad = pad_to(dg.U, kRowPad);
+    const int64_t nzb = ldz / 32, nzbp = (nzb + kZBlockPad - 1) / kZBlockPad * kZBlockPad;
+    double *St = (double *)ws_get(c, W_ST, sizeof(double) * (size_t)Upad * nzbp * 32);
+    zero(c, St + (size_t)nzb * Upad * 32, (nzbp - nzb) * Upad * 32);
+    {
+        StageTimer tm(c, MODAL_STAGE_LEGENDRE);
+        hipck(c, launch_legendre_table(g->lmax, g->lmin, d.nmu, d.ldmu, G.mu, P, c->stream), "legendre");
+    }
+    {
+        StageTimer tm(c, MODAL_STAGE_S);
+        hipck(c, launch_weights_l(d.L, g->lmin, 2.0 * p->v_power, nullptr, wl, c->stream), "weights");
+        hipck(c, launch_cbrt_weights(1, d.nmu, d.ldmu, r1, wr1, G.wmu, wz, c->stream), "cbrt weights");
+        zero_pad_rows(c, St, ldz, Upad, dg.U);
+        hipck(c, launch_s_parity(d.na, d.na, 1, d.nmu, d.ldmu, d.L, g->lmin, wl, ql, ql, P, d.ldmu, wz, Upad, St,
+                                 c->stream),
+              "Gram rows");
+    }
+    modal_problem pg = *p;
+    pg.np = p->na;
+    pg.tp = p->ta;
+    pg.tri_p = p->tri_a;
+    run_triple_gather(c, &pg, dg, prec, St, gram);
+}
+
+void blas_ok(modal_ctx c, rocblas_status st, const char *what)
+{
+    if (st != rocblas_status_success)
+        fail(c, MODAL_ERR_DEVICE, std::string(what) + ": " + rocblas_status_to_string(st));
+}
+
+// x (row-major [n][m], on the device) := gram^-1 x, gram SPD [n][n] (on the
+// device, overwritten by its Cholesky factor).  Read column major, x is its
+// transpose X' (m x n), and X' gram^-1 = X' L^-T L^-1 for gram = L L^T: two
+// triangular solves from the right.
+void solve_gram(modal_ctx c, int n, int m, double *gram, double *x)
+{
+    if (n == 0 || m == 0) return;
+    if (!c->blas) blas_ok(c, rocblas_create_handle(&c->blas), "rocblas_create_handle");
+    blas_ok(c, rocblas_set_stream(c->blas, c->stream), "rocblas_set_stream");
+    rocblas_int *info = (rocblas_int *)ws_get(c, W_INFO, sizeof(rocblas_int));
+    blas_ok(c, rocsolver_dpotrf(c->blas, rocblas_fill_lower, n, gram, n, info), "Cholesky factorisation");
+    rocblas_int hinfo = 0;
+    hipck(c, hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream), "D2H");
+    hipck(c, hipStreamSynchronize(c->stream), "synchronise");
+    need(c, hinfo == 0, MODAL_ERR_NUMERIC, "the Gram matrix <Q, Q> is not positive definite");
+    const double one = 1.0;
+    blas_ok(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                             rocblas_diagonal_non_unit, m, n, &one, gram, n, x, m),
+            "triangular solve");
+    blas_ok(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none,
+                             rocblas_diagonal_non_unit, m, n, &one, gram, n, x, m),
+            "triangular solve");
+}
+
 }  // namespace
 
 // ============================================================================
@@ -593,6 +672,7 @@ modal_status modal_destroy(modal_ctx c)
     for (auto &b : c->ws) (void)hipFree(b.p);
     free_triple_plan(c->plan64);
     free_bt_plan(c->planbt);
+    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     for (auto &pool : c->ev)
         for (auto &pr : pool) {
             (void)hipEventDestroy(pr.first);
@@ -841,6 +921,45 @@ modal_status modal_gamma(modal_ctx c, const modal_grid *g, const modal_problem *
         run_triple_gather(c, p, d, prec, f.St, o.dev);
         finish_out(c, o);
         c->fwd = FwdCache{true, false, *g, *p, f, fwd_in};
+    });
+}
+
+modal_status modal_gram(modal_ctx c, const modal_grid *g, const modal_problem *p, modal_precision prec,
+                        double *gram)
+{
+    return guarded(c, [&] {
+        check_prec(c, prec);
+        Dims d = check_grid(c, g, true);
+        modal_problem pc = *p;                // the Gram matrix reads tri_a only
+        pc.tp = 0;
+        pc.tri_p = nullptr;
+        check_problem(c, &pc, d, false, true);
+        need(c, (int64_t)p->na * p->na <= 8192, MODAL_ERR_SHAPE, "na * na above 8192");
+        need(c, gram != nullptr || p->ta == 0, MODAL_ERR_INVALID_ARG, "gram is NULL");
+        OutBuf o = dev_out(c, gram, (size_t)p->ta * p->ta, W_GRAM);
+        run_gram(c, g, &pc, d, prec, o.dev);
+        finish_out(c, o);
+    });
+}
+
+modal_status modal_gamma_modal(modal_ctx c, const modal_grid *g, const modal_problem *p, modal_precision prec,
+                               double *gamma)
+{
+    return guarded(c, [&] {
+        check_prec(c, prec);
+        Dims d = check_grid(c, g, true);
+        check_problem(c, p, d, true, true);
+        need(c, (int64_t)p->na * p->na <= 8192, MODAL_ERR_SHAPE, "na * na above 8192");
+        need(c, gamma != nullptr || (int64_t)p->ta * p->tp == 0, MODAL_ERR_INVALID_ARG, "gamma is NULL");
+        OutBuf o = dev_out(c, gamma, (size_t)p->ta * p->tp, W_GAMMA);
+        // Gamma' = <Q, Q~> in the requested precision
+        Forward f = run_forward(c, g, p, d);
+        run_triple_gather(c, p, d, prec, f.St, o.dev);
+        // <Q, Q> in FP64 (its cost is that of one radial point), then the solve
+        double *gm = (double *)ws_get(c, W_GRAM, sizeof(double) * (size_t)p->ta * p->ta);
+        run_gram(c, g, p, d, MODAL_FP64, gm);
+        solve_gram(c, p->ta, p->tp, gm, o.dev);
+        finish_out(c, o);
     });
 }
 

@@ -63,6 +63,7 @@ hipError_t launch_beta_gemm(int nl, int l0, int lmin, int L, int nk, int nr, int
 hipError_t launch_s_parity(int na, int np, int nr, int nmu, int ldmu, int L, int lmin, const double *wl,
                           const double *ql, const double *beta, const double *P, int ldP, const double *wz,
                           int64_t upad, double *S, hipStream_t s);
+// w_l = (2l+1)^(1 - v_power) / sqrt(C_l); cl == NULL reads C_l = 1
 hipError_t launch_weights_l(int L, int lmin, double v_power, const double *cl, double *wl,
                             hipStream_t s);
 hipError_t launch_cbrt_weights(int nr, int nmu, int ldmu, const double *r, const double *wr,

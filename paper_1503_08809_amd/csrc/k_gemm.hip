@@ -197,7 +197,7 @@ __global__ void k_weights_l(int L, int lmin, double v_power, const double *__res
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L) return;
     const double l2 = 2.0 * (lmin + i) + 1.0;
-    wl[i] = pow(l2, 1.0 - v_power) / sqrt(cl[i]);
+    wl[i] = pow(l2, 1.0 - v_power) / (cl ? sqrt(cl[i]) : 1.0);     // cl NULL: C_l = 1
 }
 
 __global__ void k_cbrt_weights(int nr, int nmu, int ldmu, const double *__restrict__ r,

@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
             "modal_S": [vp, G, P, ctypes.c_int, vp, vp],
             "modal_gamma_from_S": [vp, G, P, ctypes.c_int, vp, vp],
             "modal_gamma": [vp, G, P, ctypes.c_int, vp],
+            "modal_gram": [vp, G, P, ctypes.c_int, vp],
+            "modal_gamma_modal": [vp, G, P, ctypes.c_int, vp],
             "modal_gamma_backward": [vp, G, P, ctypes.c_int, vp, vp, vp],
         }
         for name, args in sig.items():
@@ -104,7 +106,8 @@ def exported_symbols():
             "modal_enable_timing", "modal_stage_times", "modal_set_forward_reuse",
             "modal_gauss_legendre",
             "modal_legendre_table", "modal_sph_bessel_table", "modal_beta", "modal_S",
-            "modal_gamma_from_S", "modal_gamma", "modal_gamma_backward"]
+            "modal_gamma_from_S", "modal_gamma", "modal_gram", "modal_gamma_modal",
+            "modal_gamma_backward"]
 
 
 def _ptr(x) -> Optional[int]:
@@ -310,6 +313,22 @@ class Projection:
                                          _PREC[precision], out.data_ptr()))
         return out
 
+
+    def gram(self, precision: str = "fp64") -> torch.Tensor:
+        """The late-time Gram matrix <Q_n, Q_m> over tri_a x tri_a."""
+        g, p = self.structs()
+        out = self.ctx.empty(self.tri_a.shape[0], self.tri_a.shape[0])
+        self.ctx.check(lib().modal_gram(self.ctx.handle, ctypes.byref(g), ctypes.byref(p),
+                                        _PREC[precision], out.data_ptr()))
+        return out
+
+    def gamma_modal(self, precision: str = "fp64") -> torch.Tensor:
+        """The full Gamma = <Q, Q>^-1 Gamma' [ta][tp]."""
+        g, p = self.structs()
+        out = self.ctx.empty(self.tri_a.shape[0], self.tri_p.shape[0])
+        self.ctx.check(lib().modal_gamma_modal(self.ctx.handle, ctypes.byref(g), ctypes.byref(p),
+                                               _PREC[precision], out.data_ptr()))
+        return out
 
     def gamma_backward(self, dgamma: torch.Tensor, precision: str = "fp64", want_q: bool = True,
                        want_delta: bool = True):
