@@ -78,6 +78,9 @@ typedef enum { MODAL_FP64 = 0, MODAL_MIXED = 1 } modal_precision;
 
 typedef enum { MODAL_GAMMA_ORDERED = 0, MODAL_GAMMA_SYMMETRIC = 1 } modal_gamma_kind;
 
+/* Rules for the integral over r (modal_r_weights). */
+typedef enum { MODAL_R_TRAPEZOID = 0, MODAL_R_HERMITE = 1 } modal_r_rule;
+
 /* Quadrature grids.  k ascending > 0; r > 0.  wk and wr are the weights of
  * the k and r rules (the r^2 of Eq. (2D) is applied by the library).  If
  * mu and wmu are both NULL the library computes the nmu-point
@@ -240,6 +243,23 @@ modal_status modal_gram(modal_ctx ctx, const modal_grid *grid, const modal_probl
  * number of <Q, Q>.  The workspace holds gram besides the forward's. */
 modal_status modal_gamma_modal(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
                                modal_precision prec, double *gamma);
+
+/* Weights w[j] of a rule for the integral of y(r) over [r[0], r[n-1]] on
+ * the given nodes, sum_j w[j] y[j]; they go into modal_grid.wr (the library
+ * multiplies by r^2 itself).  Host arrays, no context, no device work.
+ *   MODAL_R_TRAPEZOID: the trapezium rule (the rule the paper's timings use,
+ *     Modal3D algorithmic change).
+ *   MODAL_R_HERMITE: the local Hermite-cubic integrator of Eq. (hermite):
+ *     on each interval the cubic Hermite interpolant of y, with the
+ *     derivative at r_k taken as the slope of the chord from r_k to r_{k+1},
+ *     integrated exactly.  Eq. (hermite) is read with the factor
+ *     (r_{k+1} - r_k) on both derivative terms (it is printed on the first
+ *     only); at the last node the derivative is the slope of the last chord,
+ *     so the last interval reduces to the trapezium.  Exact for linear y.
+ * n >= 2 and r strictly ascending, else MODAL_ERR_SHAPE; non-finite r is
+ * MODAL_ERR_NUMERIC; an unknown rule or a NULL pointer MODAL_ERR_INVALID_ARG.
+ * The message is read with modal_last_error(NULL). */
+modal_status modal_r_weights(int32_t rule, int32_t n, const double *r, double *w);
 
 /* Gradient of a scalar loss L of Gamma (the adjoint of modal_gamma, with the
  * same grid and problem): given dgamma = dL/dGamma ([ta][tp]), writes

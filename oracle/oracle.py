@@ -436,3 +436,42 @@ def brute_force_gram_ordered(inp) -> np.ndarray:
     ta = inp.tri_a
     return G[ta[:, 0][:, None], ta[:, 0][None, :], ta[:, 1][:, None], ta[:, 1][None, :],
              ta[:, 2][:, None], ta[:, 2][None, :]]
+
+
+# ---- r rules (Modal3D algorithmic change, Eq. (hermite)) -------------------
+
+def r_rule_integral(rule: str, r, y) -> float:
+    """Integral of y(r) over [r[0], r[-1]] from its samples, interval by
+    interval.  "trapezoid": the chord of each interval.  "hermite": the cubic
+    Hermite interpolant of Eq. (hermite) on each interval [r_k, r_{k+1}],
+
+        p = h00(t) y_k + h10(t) D p'_k + h01(t) y_{k+1} + h11(t) D p'_{k+1},
+        t = (r - r_k) / D,  D = r_{k+1} - r_k,
+        h00 = 2t^3 - 3t^2 + 1, h10 = t^3 - 2t^2 + t, h01 = -2t^3 + 3t^2,
+        h11 = t^3 - t^2,
+
+    with D on both derivative terms (the printed equation drops it on the
+    second), the derivative at r_k taken as the chord slope of interval k and,
+    at the last node, as that of the last interval.  Each cubic is integrated
+    by 3-point Gauss-Legendre in t, which is exact for it."""
+    r = np.asarray(r, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = r.size
+    total = 0.0
+    if rule == "trapezoid":
+        for k in range(n - 1):
+            total += 0.5 * (r[k + 1] - r[k]) * (y[k] + y[k + 1])
+        return total
+    if rule != "hermite":
+        raise ValueError(rule)
+    slope = [(y[k + 1] - y[k]) / (r[k + 1] - r[k]) for k in range(n - 1)]
+    slope.append(slope[-1])                       # the last node
+    tq = 0.5 + 0.5 * np.array([-math.sqrt(0.6), 0.0, math.sqrt(0.6)])
+    wq = 0.5 * np.array([5.0, 8.0, 5.0]) / 9.0    # on [0, 1]
+    for k in range(n - 1):
+        D = r[k + 1] - r[k]
+        for t, wt in zip(tq, wq):
+            p = ((2 * t**3 - 3 * t**2 + 1) * y[k] + (t**3 - 2 * t**2 + t) * D * slope[k]
+                 + (-2 * t**3 + 3 * t**2) * y[k + 1] + (t**3 - t**2) * D * slope[k + 1])
+            total += D * wt * p
+    return total

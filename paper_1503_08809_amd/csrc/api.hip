@@ -1089,4 +1089,50 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
     });
 }
 
+modal_status modal_r_weights(int32_t rule, int32_t n, const double *r, double *w)
+{
+    if (!r || !w) {
+        g_last_error = "r, w must be non-NULL";
+        return MODAL_ERR_INVALID_ARG;
+    }
+    if (rule != MODAL_R_TRAPEZOID && rule != MODAL_R_HERMITE) {
+        g_last_error = "unknown r rule";
+        return MODAL_ERR_INVALID_ARG;
+    }
+    if (n < 2) {
+        g_last_error = "a rule needs n >= 2 nodes";
+        return MODAL_ERR_SHAPE;
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        if (!std::isfinite(r[j])) {
+            g_last_error = "r must be finite";
+            return MODAL_ERR_NUMERIC;
+        }
+        if (j > 0 && !(r[j] > r[j - 1])) {
+            g_last_error = "r must be strictly ascending";
+            return MODAL_ERR_SHAPE;
+        }
+    }
+    for (int32_t j = 0; j < n; ++j) w[j] = 0.0;
+    for (int32_t k = 0; k + 1 < n; ++k) {      // the trapezium part of every interval
+        const double h = r[k + 1] - r[k];
+        w[k] += 0.5 * h;
+        w[k + 1] += 0.5 * h;
+    }
+    if (rule == MODAL_R_HERMITE) {
+        // interval k adds h_k^2 / 12 (d_k - d_{k+1}), d_k = (y_{k+1} - y_k) / h_k
+        // the chord slope taken as y'(r_k) (the integrals of the two derivative
+        // basis cubics over [0, 1] are +1/12 and -1/12); d_{n-1} = d_{n-2}, so
+        // the last interval adds nothing
+        for (int32_t k = 0; k + 2 < n; ++k) {
+            const double h = r[k + 1] - r[k], h1 = r[k + 2] - r[k + 1];
+            const double c = h * h / 12.0;
+            w[k] -= c / h;
+            w[k + 1] += c / h + c / h1;
+            w[k + 2] -= c / h1;
+        }
+    }
+    return MODAL_OK;
+}
+
 }  // extern "C"

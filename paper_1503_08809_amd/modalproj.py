@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
             "modal_gram": [vp, G, P, ctypes.c_int, vp],
             "modal_gamma_modal": [vp, G, P, ctypes.c_int, vp],
             "modal_gamma_backward": [vp, G, P, ctypes.c_int, vp, vp, vp],
+            "modal_r_weights": [i32, i32, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -107,7 +108,7 @@ def exported_symbols():
             "modal_gauss_legendre",
             "modal_legendre_table", "modal_sph_bessel_table", "modal_beta", "modal_S",
             "modal_gamma_from_S", "modal_gamma", "modal_gram", "modal_gamma_modal",
-            "modal_gamma_backward"]
+            "modal_gamma_backward", "modal_r_weights"]
 
 
 def _ptr(x) -> Optional[int]:
@@ -187,6 +188,23 @@ class Context:
 
 
 # ---------------------------------------------------------------- stage calls
+R_RULES = {"trapezoid": 0, "hermite": 1}
+
+
+def r_weights(rule, r) -> np.ndarray:
+    """Weights of an r rule ("trapezoid" or "hermite", or the enum value) on
+    the nodes r, for Grid's wr (host arrays; modal_r_weights)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    w = np.empty_like(r)
+    L = lib()
+    code = R_RULES[rule] if isinstance(rule, str) else int(rule)
+    st = L.modal_r_weights(code, r.size, r.ctypes.data if r.size else None,
+                           w.ctypes.data if w.size else None)
+    if st != 0:
+        raise ModalError(st, L.modal_last_error(None).decode() or L.modal_status_str(st).decode())
+    return w
+
+
 def gauss_legendre(ctx: Context, n: int):
     x, w = ctx.empty(n), ctx.empty(n)
     ctx.check(lib().modal_gauss_legendre(ctx.handle, n, x.data_ptr(), w.data_ptr()))
