@@ -475,3 +475,83 @@ def r_rule_integral(rule: str, r, y) -> float:
                  + (-2 * t**3 + 3 * t**2) * y[k + 1] + (t**3 - t**2) * D * slope[k + 1])
             total += D * wt * p
     return total
+
+
+# ---- Eq. (3D): the direct sum over l-triples (Modal3D) ----------------------
+
+def threej000_sq_gosper(l1: int, l2: int, l3: int) -> float:
+    """The Gosper-factorial approximation of (l1 l2 l3; 0 0 0)^2 that
+    Eq. (3D) carries (its h^2 divided by prod(2l+1) / (4 pi)): with
+    L = l1 + l2 + l3 and L_i = L - 2 l_i,
+
+        (2/pi) (L + 1/3) / ((L + 1) prod_i (L_i + 1/3))
+             * sqrt(prod_i (L_i + 1/6) / (L + 1/6)),
+
+    zero unless the triangle and parity conditions hold."""
+    L = l1 + l2 + l3
+    if L % 2 or l3 > l1 + l2 or l1 > l2 + l3 or l2 > l1 + l3:
+        return 0.0
+    Li = (L - 2 * l1, L - 2 * l2, L - 2 * l3)
+    num = (L + 1.0 / 3.0) * math.sqrt((Li[0] + 1.0 / 6.0) * (Li[1] + 1.0 / 6.0) * (Li[2] + 1.0 / 6.0)
+                                      / (L + 1.0 / 6.0))
+    den = (L + 1.0) * (Li[0] + 1.0 / 3.0) * (Li[1] + 1.0 / 3.0) * (Li[2] + 1.0 / 3.0)
+    return 2.0 / math.pi * num / den
+
+
+def gamma_3d(inp, weight: str = "exact", beta_arr=None) -> np.ndarray:
+    """Gamma' of Eq. (3D), summed the way the equation and Listing 2 lay it
+    out: over sorted triples l1 <= l2 <= l3 <= min(l1 + l2, lmax) with an even
+    sum, each counted with the number of distinct orderings of the triple
+    (the summand of the symmetric form is symmetric in the l_i), of
+
+        h^2 / (v1 v2 v3 sqrt(C1 C2 C3)) = w_l1 w_l2 w_l3 (3j)^2 / (4 pi)
+
+    times the late-time product and the r integral of the primordial one.
+    Symmetric lists: both products summed over the six permutations, and the
+    1/36 of the two symmetrisations (Eq. (3D)'s 1/(72 pi^2) with the
+    Gosper form of h^2).  Ordered lists: the plain products
+    qbar_a1(l1) qbar_a2(l2) qbar_a3(l3) and beta_p1 beta_p2 beta_p3, summed
+    over every distinct ordering of the sorted triple.  weight: "exact"
+    (exact 3j, integer arithmetic) or "gosper" (the approximation printed in
+    Eq. (3D))."""
+    import itertools
+    c = inp.cfg
+    if beta_arr is None:
+        beta_arr = beta(inp)
+    w3j = threej000_sq if weight == "exact" else threej000_sq_gosper
+    wl = weights_l(inp)
+    x_r = inp.wr * inp.r ** 2                                   # r weights with r^2
+    ta, tp = inp.tri_a, inp.tri_p
+    sym = c.kind == "symmetric"
+    perms = list(itertools.permutations(range(3)))
+    out = np.zeros((ta.shape[0], tp.shape[0]))
+    for l1 in range(c.lmin, c.lmax + 1):
+        for l2 in range(l1, c.lmax + 1):
+            for l3 in range(l2 + l1 % 2, min(l1 + l2, c.lmax) + 1, 2):
+                ls = (l1, l2, l3)
+                wt = w3j(*ls)
+                if wt == 0.0:
+                    continue
+                i = [l - c.lmin for l in ls]
+                h2 = wl[i[0]] * wl[i[1]] * wl[i[2]] * wt / (4.0 * math.pi)
+                q = inp.ql[:, i].T                               # [3][na]
+                b = beta_arr[:, i, :].transpose(1, 0, 2)         # [3][np][nr]
+                orders = set(itertools.permutations(ls)) if not sym else {ls}
+                for lo in orders:
+                    # resolve repeated values: map each slot to a position of ls
+                    pos, used = [], set()
+                    for x in lo:
+                        k = next(k for k in range(3) if ls[k] == x and k not in used)
+                        used.add(k)
+                        pos.append(k)
+                    if sym:
+                        Q = sum(q[s[0], ta[:, 0]] * q[s[1], ta[:, 1]] * q[s[2], ta[:, 2]] for s in perms)
+                        X = sum((b[s[0], tp[:, 0]] * b[s[1], tp[:, 1]] * b[s[2], tp[:, 2]]) @ x_r
+                                for s in perms)
+                        mult = len(set(itertools.permutations(ls)))
+                        out += (mult * h2 / 36.0) * np.outer(Q, X)
+                    else:
+                        Q = q[pos[0], ta[:, 0]] * q[pos[1], ta[:, 1]] * q[pos[2], ta[:, 2]]
+                        X = (b[pos[0], tp[:, 0]] * b[pos[1], tp[:, 1]] * b[pos[2], tp[:, 2]]) @ x_r
+                        out += h2 * np.outer(Q, X)
+    return out
