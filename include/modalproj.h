@@ -81,6 +81,9 @@ typedef enum { MODAL_GAMMA_ORDERED = 0, MODAL_GAMMA_SYMMETRIC = 1 } modal_gamma_
 /* Rules for the integral over r (modal_r_weights). */
 typedef enum { MODAL_R_TRAPEZOID = 0, MODAL_R_HERMITE = 1 } modal_r_rule;
 
+/* The Wigner symbol in h^2 for Eq. (3D) (modal_gamma_3d). */
+typedef enum { MODAL_3J_EXACT = 0, MODAL_3J_GOSPER = 1 } modal_threej;
+
 /* Quadrature grids.  k ascending > 0; r > 0.  wk and wr are the weights of
  * the k and r rules (the r^2 of Eq. (2D) is applied by the library).  If
  * mu and wmu are both NULL the library computes the nmu-point
@@ -243,6 +246,19 @@ modal_status modal_gram(modal_ctx ctx, const modal_grid *grid, const modal_probl
  * number of <Q, Q>.  The workspace holds gram besides the forward's. */
 modal_status modal_gamma_modal(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
                                modal_precision prec, double *gamma);
+
+/* Gamma' of Eq. (3D) (Modal3D): the direct sum over l-triples with the
+ * weight h^2 of Sec. 2.1 (Eq. (weight-function)) taken from the Wigner symbol
+ * itself, MODAL_3J_EXACT (exact, by a product recurrence in FP64), or from
+ * the Gosper approximation that Eq. (3D) prints (MODAL_3J_GOSPER, within
+ * 2.3 % of the exact symbol for l >= 2), and no mu integral: the form the
+ * paper keeps for bases where the separable form is unstable.  With the exact
+ * symbol it equals modal_gamma's Gamma' up to rounding.  Same grid and
+ * problem as modal_gamma (nmu, mu, wmu unused; both kinds); FP64 throughout.
+ * np * na <= 1280 (the workspace holds the full moment tensor,
+ * 8 (np na)^3 bytes, plus about 4 GiB of operands).  gamma: [ta][tp]. */
+modal_status modal_gamma_3d(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
+                            int32_t threej, double *gamma);
 
 /* Weights w[j] of a rule for the integral of y(r) over [r[0], r[n-1]] on
  * the given nodes, sum_j w[j] y[j]; they go into modal_grid.wr (the library

@@ -24,6 +24,7 @@ enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
     W_S32, W_SH, W_SL, W_GAMMA,
     W_INVA, W_INVP, W_H, W_SHAT, W_BHAT, W_AHAT, W_DQ, W_DD, W_GRAM, W_INFO,
+    W_G3, W_A3, W_B3, W_C3, W_K3, W_T3,
     W_IN0, NSLOTS = W_IN0 + 16
 };
 
@@ -601,6 +602,86 @@ void blas_ok(modal_ctx c, rocblas_status st, const char *what)
         fail(c, MODAL_ERR_DEVICE, std::string(what) + ": " + rocblas_status_to_string(st));
 }
 
+void blas_bind(modal_ctx c)
+{
+    if (!c->blas) blas_ok(c, rocblas_create_handle(&c->blas), "rocblas_create_handle");
+    blas_ok(c, rocblas_set_stream(c->blas, c->stream), "rocblas_set_stream");
+}
+
+// Gamma' of Eq. (3D) with the exact (threej = MODAL_3J_EXACT) or Gosper
+// symbol: the moment tensor T contracted one l at a time (k_modal3d.hip),
+// then gathered.  The r axis is taken in batches so that the G and A
+// operands stay within about 2 GiB each.
+void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, const Dims &d, int threej,
+                  double *gamma)
+{
+    Grid G{};
+    G.k = dev_in(c, g->k, d.nk);
+    G.wk = dev_in(c, g->wk, d.nk);
+    G.r = dev_in(c, g->r, d.nr);
+    G.wr = dev_in(c, g->wr, d.nr);
+    const double *delta = dev_in(c, p->delta, (size_t)d.L * d.nk);
+    const double *qk = dev_in(c, p->qk, (size_t)d.np * d.nk);
+    const double *cl = dev_in(c, p->cl, (size_t)d.L);
+    const double *ql = dev_in(c, p->ql, (size_t)d.na * d.L);
+    double *beta = (double *)ws_get(c, W_BETA, sizeof(double) * (size_t)d.np * d.L * d.nr);
+    run_beta(c, g, d, G, delta, qk, beta);
+    double *wl = (double *)ws_get(c, W_WL, sizeof(double) * d.L);
+    hipck(c, launch_weights_l(d.L, g->lmin, p->v_power, cl, wl, c->stream), "weights");
+
+    const int L = d.L, U = d.U;
+    // parity classes of l in [lmin, lmax]: even first in the l' order
+    const int lE0 = g->lmin + (g->lmin & 1), lO0 = g->lmin + 1 - (g->lmin & 1);
+    const int nE = lE0 <= g->lmax ? (g->lmax - lE0) / 2 + 1 : 0;
+    const int nO = lO0 <= g->lmax ? (g->lmax - lO0) / 2 + 1 : 0;
+    const int l0c[2] = {lE0, lO0}, nc[2] = {nE, nO}, offc[2] = {0, nE};
+    const size_t per_r = (size_t)L * U * sizeof(double);
+    const int nrb = (int)std::max<size_t>(1, std::min<size_t>((size_t)d.nr, ((size_t)2 << 30) / per_r));
+    double *Gb = (double *)ws_get(c, W_G3, per_r * nrb);
+    double *Ab = (double *)ws_get(c, W_A3, per_r * nrb);
+    double *Bb = (double *)ws_get(c, W_B3, sizeof(double) * (size_t)U * U * nrb);
+    double *Cb = (double *)ws_get(c, W_C3, sizeof(double) * (size_t)U * nrb);
+    double *Kb = (double *)ws_get(c, W_K3, sizeof(double) * std::max<size_t>(1, (size_t)std::max(nE, nO) * std::max(nE, nO)));
+    const size_t tn = (size_t)U * U * U;
+    double *T = (double *)ws_get(c, W_T3, sizeof(double) * tn);
+    zero(c, T, (int64_t)tn);
+    blas_bind(c);
+    const double one = 1.0, nil = 0.0;
+    for (int r0 = 0; r0 < d.nr; r0 += nrb) {
+        const int nb = std::min(nrb, d.nr - r0);
+        hipck(c, launch_build_g3(L, nE, lE0, lO0, g->lmin, d.nr, d.np, d.na, r0, nb, wl, ql, beta, Gb, c->stream),
+              "Eq. (3D) operand");
+        for (int l1 = g->lmin; l1 <= g->lmax; ++l1) {
+            const int p1 = l1 & 1;
+            // with one parity class empty, some rows of A have no l3 at all
+            if (nE == 0 || nO == 0) zero(c, Ab, (int64_t)L * nb * U);
+            for (int par2 = 0; par2 < 2; ++par2) {
+                // class 0 = even l, 1 = odd l; l3 has the parity of l1 + l2
+                const int par3 = (p1 + par2) & 1;
+                const int n2 = nc[par2], n3 = nc[par3];
+                if (n2 == 0 || n3 == 0) continue;
+                hipck(c, launch_build_k3(l1, l0c[par2], n2, l0c[par3], n3, threej == MODAL_3J_GOSPER, Kb, c->stream),
+                      "Eq. (3D) symbols");
+                blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n2, nb * U, n3, &one,
+                                         Kb, n2, Gb + offc[par3], L, &nil, Ab + offc[par2], L),
+                        "Eq. (3D) stage 1");
+            }
+            blas_ok(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, U, U,
+                                                     L, &one, Gb, L, (rocblas_stride)U * L, Ab, L,
+                                                     (rocblas_stride)U * L, &nil, Bb, U, (rocblas_stride)U * U, nb),
+                    "Eq. (3D) stage 2");
+            const int lp1 = p1 == 0 ? (l1 - lE0) / 2 : nE + (l1 - lO0) / 2;
+            hipck(c, launch_c3(L, lp1, U, r0, nb, G.r, G.wr, Gb, Cb, c->stream), "Eq. (3D) radial weights");
+            blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, U, U * U, nb, &one, Cb,
+                                     U, Bb, U * U, &one, T, U),
+                    "Eq. (3D) stage 3");
+        }
+    }
+    const int *ta = dev_in(c, p->tri_a, (size_t)p->ta * 3);
+    const int *tp = dev_in(c, p->tri_p, (size_t)p->tp * 3);
+    hipck(c, launch_gather3(p->kind, p->ta, p->tp, ta, tp, d.np, U, T, gamma, c->stream), "Eq. (3D) gather");
+}
+
 // x (row-major [n][m], on the device) := gram^-1 x, gram SPD [n][n] (on the
 // device, overwritten by its Cholesky factor).  Read column major, x is its
 // transpose X' (m x n), and X' gram^-1 = X' L^-T L^-1 for gram = L L^T: two
@@ -1086,6 +1167,22 @@ modal_status modal_gamma_backward(modal_ctx c, const modal_grid *g, const modal_
         finish_out(c, oq);
         finish_out(c, od);
         c->fwd = FwdCache{true, false, *g, *p, f, fwd_in};
+    });
+}
+
+modal_status modal_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, int32_t threej,
+                            double *gamma)
+{
+    return guarded(c, [&] {
+        need(c, threej == MODAL_3J_EXACT || threej == MODAL_3J_GOSPER, MODAL_ERR_INVALID_ARG,
+             "threej must be MODAL_3J_EXACT or MODAL_3J_GOSPER");
+        need(c, gamma != nullptr, MODAL_ERR_INVALID_ARG, "gamma must be non-NULL");
+        Dims d = check_grid(c, g, false);
+        check_problem(c, p, d, true, true);
+        need(c, d.U <= 1280, MODAL_ERR_SHAPE, "np * na above 1280: the moment tensor (8 (np na)^3 bytes) is too large");
+        OutBuf o = dev_out(c, gamma, (size_t)p->ta * p->tp, W_GAMMA);
+        run_gamma_3d(c, g, p, d, threej, o.dev);
+        finish_out(c, o);
     });
 }
 

@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
             "modal_gamma_modal": [vp, G, P, ctypes.c_int, vp],
             "modal_gamma_backward": [vp, G, P, ctypes.c_int, vp, vp, vp],
             "modal_r_weights": [i32, i32, vp, vp],
+            "modal_gamma_3d": [vp, G, P, i32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -108,7 +109,7 @@ def exported_symbols():
             "modal_gauss_legendre",
             "modal_legendre_table", "modal_sph_bessel_table", "modal_beta", "modal_S",
             "modal_gamma_from_S", "modal_gamma", "modal_gram", "modal_gamma_modal",
-            "modal_gamma_backward", "modal_r_weights"]
+            "modal_gamma_backward", "modal_r_weights", "modal_gamma_3d"]
 
 
 def _ptr(x) -> Optional[int]:
@@ -346,6 +347,15 @@ class Projection:
         out = self.ctx.empty(self.tri_a.shape[0], self.tri_p.shape[0])
         self.ctx.check(lib().modal_gamma_modal(self.ctx.handle, ctypes.byref(g), ctypes.byref(p),
                                                _PREC[precision], out.data_ptr()))
+        return out
+
+    def gamma_3d(self, threej: str = "exact") -> torch.Tensor:
+        """Gamma' of Eq. (3D) [ta][tp]: the direct sum over l-triples with the
+        exact ("exact") or Gosper ("gosper") Wigner symbol, FP64."""
+        g, p = self.structs()
+        out = self.ctx.empty(self.tri_a.shape[0], self.tri_p.shape[0])
+        self.ctx.check(lib().modal_gamma_3d(self.ctx.handle, ctypes.byref(g), ctypes.byref(p),
+                                            {"exact": 0, "gosper": 1}[threej], out.data_ptr()))
         return out
 
     def gamma_backward(self, dgamma: torch.Tensor, precision: str = "fp64", want_q: bool = True,
