@@ -24,7 +24,7 @@ enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
     W_S32, W_SH, W_SL, W_GAMMA,
     W_INVA, W_INVP, W_H, W_SHAT, W_BHAT, W_AHAT, W_DQ, W_DD, W_GRAM, W_INFO,
-    W_G3, W_A3, W_B3, W_C3, W_K3, W_T3,
+    W_G3, W_A3, W_B3, W_C3, W_K3, W_T3, W_P3,
     W_IN0, NSLOTS = W_IN0 + 16
 };
 
@@ -612,6 +612,8 @@ void blas_bind(modal_ctx c)
 // symbol: the moment tensor T contracted one l at a time (k_modal3d.hip),
 // then gathered.  The r axis is taken in batches so that the G and A
 // operands stay within about 2 GiB each.
+constexpr int kRowChunk3d = 128;
+
 void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, const Dims &d, int threej,
                   double *gamma)
 {
@@ -642,7 +644,11 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
     double *Bb = (double *)ws_get(c, W_B3, sizeof(double) * (size_t)U * U * nrb);
     double *Cb = (double *)ws_get(c, W_C3, sizeof(double) * (size_t)U * nrb);
     double *Kb = (double *)ws_get(c, W_K3, sizeof(double) * std::max<size_t>(1, (size_t)std::max(nE, nO) * std::max(nE, nO)));
-    const size_t tn = (size_t)U * U * U;
+    // T(u1, u2 <= u3) only (T is symmetric in its last two indices), the
+    // (u2, u3) pairs packed column by column: NT = U (U + 1) / 2 columns
+    const int NT = U * (U + 1) / 2;
+    double *Pb = (double *)ws_get(c, W_P3, sizeof(double) * (size_t)NT * nrb);
+    const size_t tn = (size_t)U * NT;
     double *T = (double *)ws_get(c, W_T3, sizeof(double) * tn);
     zero(c, T, (int64_t)tn);
     blas_bind(c);
@@ -662,18 +668,50 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
                 if (n2 == 0 || n3 == 0) continue;
                 hipck(c, launch_build_k3(l1, l0c[par2], n2, l0c[par3], n3, threej == MODAL_3J_GOSPER, Kb, c->stream),
                       "Eq. (3D) symbols");
-                blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n2, nb * U, n3, &one,
-                                         Kb, n2, Gb + offc[par3], L, &nil, Ab + offc[par2], L),
-                        "Eq. (3D) stage 1");
+                // rows in chunks, each multiplied only over the l3 columns its
+                // triangles reach: |l1 - l2| <= l3 <= l1 + l2 (half the block
+                // on average)
+                for (int i2a = 0; i2a < n2; i2a += kRowChunk3d) {
+                    const int i2b = std::min(n2, i2a + kRowChunk3d);
+                    const int l2a = l0c[par2] + 2 * i2a, l2b = l0c[par2] + 2 * (i2b - 1);
+                    const int lo = l1 < l2a ? l2a - l1 : (l1 > l2b ? l1 - l2b : 0);
+                    const int hi = l1 + l2b;
+                    const int c0 = std::max(0, (lo - l0c[par3] + 1) / 2);
+                    const int c1 = hi < l0c[par3] ? -1 : std::min(n3 - 1, (hi - l0c[par3]) / 2);
+                    if (c1 < c0) {
+                        for (int col = 0; col < nb * U; ++col)
+                            zero(c, Ab + (size_t)col * L + offc[par2] + i2a, i2b - i2a);
+                        continue;
+                    }
+                    blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, i2b - i2a, nb * U,
+                                             c1 - c0 + 1, &one, Kb + (size_t)c0 * n2 + i2a, n2,
+                                             Gb + offc[par3] + c0, L, &nil, Ab + offc[par2] + i2a, L),
+                            "Eq. (3D) stage 1");
+                }
             }
-            blas_ok(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none, U, U,
-                                                     L, &one, Gb, L, (rocblas_stride)U * L, Ab, L,
-                                                     (rocblas_stride)U * L, &nil, Bb, U, (rocblas_stride)U * U, nb),
-                    "Eq. (3D) stage 2");
+            // B_r = G_r^T K G_r is symmetric (K is symmetric in l2, l3): of
+            // its 2 x 2 blocks only the three on or above the diagonal, then
+            // the upper triangle packed column by column
+            {
+                const int h = (U + 1) / 2;
+                const int off[3][2] = {{0, 0}, {0, h}, {h, h}};
+                for (int b = 0; b < 3; ++b) {
+                    const int u0 = off[b][0], v0 = off[b][1];
+                    const int mu = (u0 == 0 ? h : U - h), nv = (v0 == 0 ? h : U - h);
+                    if (mu <= 0 || nv <= 0) continue;
+                    blas_ok(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
+                                                             mu, nv, L, &one, Gb + (size_t)u0 * L, L,
+                                                             (rocblas_stride)U * L, Ab + (size_t)v0 * L, L,
+                                                             (rocblas_stride)U * L, &nil, Bb + u0 + (size_t)v0 * U, U,
+                                                             (rocblas_stride)U * U, nb),
+                            "Eq. (3D) stage 2");
+                }
+            }
+            hipck(c, launch_pack3(U, nb, Bb, Pb, c->stream), "Eq. (3D) pack");
             const int lp1 = p1 == 0 ? (l1 - lE0) / 2 : nE + (l1 - lO0) / 2;
             hipck(c, launch_c3(L, lp1, U, r0, nb, G.r, G.wr, Gb, Cb, c->stream), "Eq. (3D) radial weights");
-            blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, U, U * U, nb, &one, Cb,
-                                     U, Bb, U * U, &one, T, U),
+            blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, U, NT, nb, &one, Cb,
+                                     U, Pb, NT, &one, T, U),
                     "Eq. (3D) stage 3");
         }
     }

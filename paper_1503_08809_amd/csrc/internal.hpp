@@ -179,12 +179,14 @@ hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const doub
 // Eq. (3D) (k_modal3d.hip): operand G[(rb U + u) L + l'] (l' parity-sorted,
 // even l first) for r in [r0, r0 + nrb); the band of 2 (3j)^2 for one l1 and
 // one pair of parity classes, K[i3 n2 + i2]; the r weights times the row l1'
-// of G, C[rb U + u]; and the gather of Gamma' from T[u1 + U (u2 + U u3)].
+// of G, C[rb U + u]; the packing of the upper triangles of B_r; and the
+// gather of Gamma' from T[u1 + U (u3 (u3 + 1) / 2 + u2)], u2 <= u3.
 hipError_t launch_build_g3(int L, int nE, int lE0, int lO0, int lmin, int nr, int np, int na, int r0, int nrb,
                            const double *wl, const double *ql, const double *beta, double *G, hipStream_t s);
 hipError_t launch_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper, double *K, hipStream_t s);
 hipError_t launch_c3(int L, int lp1, int U, int r0, int nrb, const double *r, const double *wr, const double *G,
                      double *C, hipStream_t s);
+hipError_t launch_pack3(int U, int nrb, const double *B, double *P, hipStream_t s);
 hipError_t launch_gather3(int kind, int ta, int tp, const int *tri_a, const int *tri_p, int np, int U,
                           const double *T, double *gamma, hipStream_t s);
 

@@ -15,6 +15,8 @@
 //   A_r(l2, u3) = Sum_l3 K(l1, l2, l3) G_u3(l3, r)          (stage 1)
 //   B_r(u2, u3) = Sum_l2 G_u2(l2, r) A_r(l2, u3)            (stage 2)
 //   T(u1, u2, u3) += Sum_r wr r^2 G_u1(l1, r) B_r(u2, u3)   (stage 3)
+// B_r and T are symmetric in (u2, u3): stage 2 forms one triangle, which is
+// packed, and stage 3 and T run over the packed pairs only.
 // The l index is stored parity-sorted (even l first): for a given l1, K is
 // non-zero only where l1 + l2 + l3 is even, so stage 1 is two dense products
 // of half size (one per parity of l2).  The three stages are plain GEMMs
@@ -122,7 +124,21 @@ __global__ void k_c3(int L, int lp1, int U, int r0, int nrb, const double *__res
     C[i] = wr[r0 + rb] * x * x * G[(size_t)i * L + lp1];
 }
 
-// Gamma[n][m] from T(u1, u2, u3) = T[u1 + U (u2 + U u3)].
+// P[rb NT + u3 (u3 + 1) / 2 + u2] = B[rb U^2 + u2 + U u3] for u2 <= u3.
+__global__ void k_pack3(int U, int nrb, const double *__restrict__ B, double *__restrict__ P)
+{
+    const int64_t n = (int64_t)U * U * nrb;
+    const int64_t NT = (int64_t)U * (U + 1) / 2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int u2 = (int)(i % U);
+        const int64_t rest = i / U;
+        const int u3 = (int)(rest % U), rb = (int)(rest / U);
+        if (u2 <= u3) P[rb * NT + (int64_t)u3 * (u3 + 1) / 2 + u2] = B[i];
+    }
+}
+
+// Gamma[n][m] from T(u1, u2, u3), symmetric, stored for u2 <= u3 as
+// T[u1 + U (u3 (u3 + 1) / 2 + u2)].
 __global__ void k_gather3(int kind, int ta, int tp, const int *__restrict__ tri_a, const int *__restrict__ tri_p,
                           int np, int U, const double *__restrict__ T, double *__restrict__ gamma)
 {
@@ -131,8 +147,11 @@ __global__ void k_gather3(int kind, int ta, int tp, const int *__restrict__ tri_
     const int n = (int)(i / tp), m = (int)(i % tp);
     const int a0 = tri_a[3 * n] * np, a1 = tri_a[3 * n + 1] * np, a2 = tri_a[3 * n + 2] * np;
     const int p0 = tri_p[3 * m], p1 = tri_p[3 * m + 1], p2 = tri_p[3 * m + 2];
-    const size_t U1 = (size_t)U, U2 = U1 * U1;
-    auto at = [&](int x, int y, int z) { return T[(size_t)(a0 + x) + U1 * (a1 + y) + U2 * (a2 + z)]; };
+    auto at = [&](int x, int y, int z) {
+        const int v = a1 + y, w = a2 + z;
+        const int lo = min(v, w), hi = max(v, w);
+        return T[(size_t)(a0 + x) + (size_t)U * ((size_t)hi * (hi + 1) / 2 + lo)];
+    };
     if (kind == MODAL_GAMMA_ORDERED) {
         gamma[i] = at(p0, p1, p2) / (8.0 * kPi);
         return;
@@ -166,6 +185,14 @@ hipError_t launch_c3(int L, int lp1, int U, int r0, int nrb, const double *r, co
 {
     const int n = U * nrb;
     hipLaunchKernelGGL(k_c3, dim3((n + 255) / 256), dim3(256), 0, s, L, lp1, U, r0, nrb, r, wr, G, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack3(int U, int nrb, const double *B, double *P, hipStream_t s)
+{
+    const int64_t n = (int64_t)U * U * nrb;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_pack3, dim3(blocks), dim3(256), 0, s, U, nrb, B, P);
     return hipGetLastError();
 }
 

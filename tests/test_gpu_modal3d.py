@@ -58,6 +58,17 @@ def test_3d_vs_oracle(mp, ctx, oracle, threej, kind, n1, lmax, nr, nk):
     assert err <= 1e-12
 
 
+@pytest.mark.parametrize("kind,n1,lmax,nr", [("symmetric", 4, 300, 6), ("ordered", 3, 517, 5)])
+def test_3d_vs_separable(mp, ctx, kind, n1, lmax, nr):
+    """Several 128-row chunks of the l3 band and an odd lmax: Eq. (3D) (exact
+    symbol) against Eq. (2D) on the GPU."""
+    inp = synth.make_inputs(synth.small_config(lmax=lmax, nk=300, nr=nr, n1=n1, kind=kind, seed_index=98))
+    pr = mp.projection_from_inputs(ctx, inp)
+    err = normwise(_np(pr.gamma_3d("exact")), _np(pr.gamma("fp64")))
+    print(f"Eq. (3D) vs Eq. (2D) {kind} lmax={lmax}: {err:.2e}")
+    assert err <= 1e-10
+
+
 def test_3d_lmax1000(mp, ctx):
     """lmax = 1000, Nr = 300, 1540 x 1540 symmetric: Eq. (3D) with the exact
     symbol against Eq. (2D) on the GPU and against stored oracle entries."""
