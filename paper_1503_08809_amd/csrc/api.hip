@@ -659,13 +659,15 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
               "Eq. (3D) operand");
         for (int l1 = g->lmin; l1 <= g->lmax; ++l1) {
             const int p1 = l1 & 1;
-            // with one parity class empty, some rows of A have no l3 at all
-            if (nE == 0 || nO == 0) zero(c, Ab, (int64_t)L * nb * U);
             for (int par2 = 0; par2 < 2; ++par2) {
                 // class 0 = even l, 1 = odd l; l3 has the parity of l1 + l2
                 const int par3 = (p1 + par2) & 1;
                 const int n2 = nc[par2], n3 = nc[par3];
-                if (n2 == 0 || n3 == 0) continue;
+                if (n2 == 0) continue;
+                if (n3 == 0) {      // no l3 of the needed parity at all
+                    hipck(c, launch_zero_rows3(L, offc[par2], n2, (int64_t)nb * U, Ab, c->stream), "Eq. (3D) empty rows");
+                    continue;
+                }
                 hipck(c, launch_build_k3(l1, l0c[par2], n2, l0c[par3], n3, threej == MODAL_3J_GOSPER, Kb, c->stream),
                       "Eq. (3D) symbols");
                 // rows in chunks, each multiplied only over the l3 columns its
@@ -678,9 +680,9 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
                     const int hi = l1 + l2b;
                     const int c0 = std::max(0, (lo - l0c[par3] + 1) / 2);
                     const int c1 = hi < l0c[par3] ? -1 : std::min(n3 - 1, (hi - l0c[par3]) / 2);
-                    if (c1 < c0) {
-                        for (int col = 0; col < nb * U; ++col)
-                            zero(c, Ab + (size_t)col * L + offc[par2] + i2a, i2b - i2a);
+                    if (c1 < c0) {      // no triangle reaches an l3 of this class
+                        hipck(c, launch_zero_rows3(L, offc[par2] + i2a, i2b - i2a, (int64_t)nb * U, Ab, c->stream),
+                              "Eq. (3D) empty rows");
                         continue;
                     }
                     blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, i2b - i2a, nb * U,

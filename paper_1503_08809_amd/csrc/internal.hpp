@@ -187,6 +187,7 @@ hipError_t launch_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper,
 hipError_t launch_c3(int L, int lp1, int U, int r0, int nrb, const double *r, const double *wr, const double *G,
                      double *C, hipStream_t s);
 hipError_t launch_pack3(int U, int nrb, const double *B, double *P, hipStream_t s);
+hipError_t launch_zero_rows3(int64_t ld, int row0, int nrows, int64_t ncols, double *A, hipStream_t s);
 hipError_t launch_gather3(int kind, int ta, int tp, const int *tri_a, const int *tri_p, int np, int U,
                           const double *T, double *gamma, hipStream_t s);
 

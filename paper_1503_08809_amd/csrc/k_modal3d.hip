@@ -137,6 +137,15 @@ __global__ void k_pack3(int U, int nrb, const double *__restrict__ B, double *__
     }
 }
 
+// Zero rows [row0, row0 + nrows) of every column of a column-major matrix
+// with leading dimension ld and ncols columns.
+__global__ void k_zero_rows3(int64_t ld, int row0, int nrows, int64_t ncols, double *__restrict__ A)
+{
+    const int64_t n = (int64_t)nrows * ncols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        A[(i / nrows) * ld + row0 + i % nrows] = 0.0;
+}
+
 // Gamma[n][m] from T(u1, u2, u3), symmetric, stored for u2 <= u3 as
 // T[u1 + U (u3 (u3 + 1) / 2 + u2)].
 __global__ void k_gather3(int kind, int ta, int tp, const int *__restrict__ tri_a, const int *__restrict__ tri_p,
@@ -185,6 +194,15 @@ hipError_t launch_c3(int L, int lp1, int U, int r0, int nrb, const double *r, co
 {
     const int n = U * nrb;
     hipLaunchKernelGGL(k_c3, dim3((n + 255) / 256), dim3(256), 0, s, L, lp1, U, r0, nrb, r, wr, G, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_rows3(int64_t ld, int row0, int nrows, int64_t ncols, double *A, hipStream_t s)
+{
+    const int64_t n = (int64_t)nrows * ncols;
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero_rows3, dim3(blocks), dim3(256), 0, s, ld, row0, nrows, ncols, A);
     return hipGetLastError();
 }
 

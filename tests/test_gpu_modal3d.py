@@ -58,6 +58,28 @@ def test_3d_vs_oracle(mp, ctx, oracle, threej, kind, n1, lmax, nr, nk):
     assert err <= 1e-12
 
 
+@pytest.mark.parametrize("l", [2, 3])
+def test_3d_single_l(mp, ctx, oracle, l):
+    """One multipole (lmin = lmax = l): for even l the single triple (l, l, l)
+    against the oracle; for odd l every symbol vanishes by parity (no l3 of
+    the needed parity exists), and Gamma' must be exactly zero."""
+    import dataclasses
+    import warnings
+    cfg = dataclasses.replace(synth.small_config(lmax=l, nk=30, nr=3, n1=2, kind="symmetric", seed_index=99),
+                              lmin=l)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")                       # the l basis of one point is 0/0
+        inp = synth.make_inputs(cfg)
+    inp.ql[:] = np.random.default_rng(5).standard_normal(inp.ql.shape)
+    pr = mp.projection_from_inputs(ctx, inp)
+    g = _np(pr.gamma_3d("exact"))
+    if l % 2:
+        assert np.all(g == 0.0)
+    else:
+        ref = oracle.gamma_3d(inp)
+        assert np.abs(ref).max() > 0 and normwise(g, ref) <= 1e-13
+
+
 @pytest.mark.parametrize("kind,n1,lmax,nr", [("symmetric", 4, 300, 6), ("ordered", 3, 517, 5)])
 def test_3d_vs_separable(mp, ctx, kind, n1, lmax, nr):
     """Several 128-row chunks of the l3 band and an odd lmax: Eq. (3D) (exact
