@@ -247,6 +247,15 @@ def main() -> int:
     def nerr(a, b):
         return float((a - b).abs().max() / b.abs().max())
 
+    def elem_large(a, b):
+        # elementwise relative error over the entries with |b| >= 1e-3 max|b|
+        big = b.abs() >= 1e-3 * b.abs().max()
+        return float(((a - b).abs()[big] / b.abs()[big]).max())
+
+    def pct_rmse(a, b):
+        # the percentage RMSE of the unit-normalised Gamma (performance section)
+        return float(100.0 * ((a / a.norm() - b / b.norm()) ** 2).mean().sqrt())
+
     paths = {}
     main_prec = args.precision
     ref = None
@@ -260,6 +269,8 @@ def main() -> int:
         if ref is not None:
             m = paths["mixed"]
             m["gamma_normwise_err_vs_fp64"] = nerr(out, ref[0])
+            m["gamma_elementwise_large_err_vs_fp64"] = elem_large(out, ref[0])
+            m["gamma_pct_rmse_vs_fp64"] = pct_rmse(out, ref[0])
             if adjoint:
                 m["dq_normwise_err_vs_fp64"] = nerr(gm[0], ref[1][0])
                 m["ddelta_normwise_err_vs_fp64"] = nerr(gm[1], ref[1][1])
