@@ -150,6 +150,42 @@ def cpu_baseline(inp, adjoint: bool = True) -> dict:
             "kind": "oracle", "sample": sample, "stages_s": t}
 
 
+def measure_ceilings() -> dict:
+    """What the libraries reach on this GPU, next to the datasheet peaks: a
+    plain square GEMM per dtype (torch.matmul, 2-D, contiguous operands) and a
+    device-to-device copy, timed with events over repeated launches."""
+    import torch
+    dev = torch.device("cuda", 0)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3 / reps
+
+    out = {}
+    for name, dt, n, reps in (("bf16", torch.bfloat16, 16384, 20), ("fp32", torch.float32, 8192, 10),
+                              ("fp64", torch.float64, 8192, 5)):
+        x = torch.randn(n, n, device=dev, dtype=torch.float32).to(dt)
+        y = torch.randn(n, n, device=dev, dtype=torch.float32).to(dt)
+        sec = timed(lambda: torch.matmul(x, y), reps)
+        out[f"gemm_{name}_tflops"] = 2.0 * n ** 3 / sec / 1e12
+        out[f"gemm_{name}_size"] = n
+        del x, y
+    n = 1 << 29                                               # 4 GiB of doubles
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    sec = timed(lambda: dst.copy_(src), 10)
+    out["copy_gbs"] = 2.0 * n * 8 / sec / 1e9                 # bytes read + written
+    out["copy_bytes"] = n * 8
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,11 +199,16 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="measure library GEMM and copy ceilings on this GPU, print them, exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU r-sharding is a design, not built)", file=sys.stderr)
         return 2
+    if args.ceilings:
+        print(json.dumps(measure_ceilings()))
+        return 0
 
     import torch
     from paper_1503_08809_amd import modalproj as mp
