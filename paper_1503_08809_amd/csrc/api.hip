@@ -24,7 +24,7 @@ enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
     W_S32, W_SH, W_SL, W_GAMMA,
     W_INVA, W_INVP, W_H, W_SHAT, W_BHAT, W_AHAT, W_DQ, W_DD, W_GRAM, W_INFO,
-    W_G3, W_A3, W_B3, W_C3, W_K3, W_T3, W_P3,
+    W_G3, W_A3, W_B3, W_C3, W_K3, W_T3, W_P3, W_V3,
     W_IN0, NSLOTS = W_IN0 + 16
 };
 
@@ -651,6 +651,9 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
     const size_t tn = (size_t)U * NT;
     double *T = (double *)ws_get(c, W_T3, sizeof(double) * tn);
     zero(c, T, (int64_t)tn);
+    // start values of the symbol bands, (l1 l2 |l1 - l2|; 000)^2 by max and min
+    double *V = (double *)ws_get(c, W_V3, sizeof(double) * ((size_t)g->lmax + 1) * (g->lmax + 2) / 2);
+    hipck(c, launch_start3(g->lmax, V, c->stream), "Eq. (3D) band starts");
     blas_bind(c);
     const double one = 1.0, nil = 0.0;
     for (int r0 = 0; r0 < d.nr; r0 += nrb) {
@@ -668,7 +671,7 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
                     hipck(c, launch_zero_rows3(L, offc[par2], n2, (int64_t)nb * U, Ab, c->stream), "Eq. (3D) empty rows");
                     continue;
                 }
-                hipck(c, launch_build_k3(l1, l0c[par2], n2, l0c[par3], n3, threej == MODAL_3J_GOSPER, Kb, c->stream),
+                hipck(c, launch_build_k3(l1, l0c[par2], n2, l0c[par3], n3, threej == MODAL_3J_GOSPER, V, Kb, c->stream),
                       "Eq. (3D) symbols");
                 // rows in chunks, each multiplied only over the l3 columns its
                 // triangles reach: |l1 - l2| <= l3 <= l1 + l2 (half the block

@@ -53,14 +53,19 @@ __global__ void k_build_g3(int L, int nE, int lE0, int lO0, int lmin, int nr, in
 
 // (l1 l2 l3; 0 0 0)^2 at l3 = |l1 - l2|: with b = max, s = min,
 // C(b, s)^2 / ((2b + 1) C(2b, 2s)) = Prod_{j=1..s} (2j - 1)(b - j + 1) / (j (2b - 2j + 1)) / (2b + 1),
-// a product of factors of order one.
-__device__ double threej_sq_start(int l1, int l2)
+// a product of factors of order one.  V[b (b + 1) / 2 + s] holds it for
+// 0 <= s <= b <= lmax: one thread per b runs the product over s.
+__global__ void k_start3(int lmax, double *__restrict__ V)
 {
-    const int b = max(l1, l2), s = min(l1, l2);
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > lmax) return;
+    double *row = V + (size_t)b * (b + 1) / 2;
     double v = 1.0 / (2.0 * b + 1.0);
-    for (int j = 1; j <= s; ++j)
+    row[0] = v;
+    for (int j = 1; j <= b; ++j) {
         v *= ((2.0 * j - 1.0) * (double)(b - j + 1)) / ((double)j * (2.0 * b - 2.0 * j + 1.0));
-    return v;
+        row[j] = v;
+    }
 }
 
 // (3j)^2 at l3 + 2 over (3j)^2 at l3 (same l1, l2), from the factorial form
@@ -87,14 +92,16 @@ __device__ __forceinline__ double threej_sq_gosper(int l1, int l2, int l3)
 // (l20, l30 of the two parity classes, l1 + l2 + l3 even); zero outside
 // the triangle |l1 - l2| <= l3 <= l1 + l2.  One thread per l2 walks l3 upward
 // from |l1 - l2| with the step ratio (exact) or evaluates the Gosper form.
-__global__ void k_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper, double *__restrict__ K)
+__global__ void k_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper, const double *__restrict__ V,
+                           double *__restrict__ K)
 {
     const int i2 = blockIdx.x * blockDim.x + threadIdx.x;
     if (i2 >= n2) return;
     const int l2 = l20 + 2 * i2;
     const int lo = abs(l1 - l2), hi = l1 + l2;
     int lc = lo;
-    double v = gosper ? 0.0 : threej_sq_start(l1, l2);
+    const int b = max(l1, l2);
+    double v = gosper ? 0.0 : V[(size_t)b * (b + 1) / 2 + min(l1, l2)];
     for (int i3 = 0; i3 < n3; ++i3) {
         const int l3 = l30 + 2 * i3;
         double out = 0.0;
@@ -182,10 +189,17 @@ hipError_t launch_build_g3(int L, int nE, int lE0, int lO0, int lmin, int nr, in
     return hipGetLastError();
 }
 
-hipError_t launch_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper, double *K, hipStream_t s)
+hipError_t launch_start3(int lmax, double *V, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_start3, dim3((lmax + 64) / 64), dim3(64), 0, s, lmax, V);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper, const double *V, double *K,
+                           hipStream_t s)
 {
     if (n2 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_k3, dim3((n2 + 63) / 64), dim3(64), 0, s, l1, l20, n2, l30, n3, gosper, K);
+    hipLaunchKernelGGL(k_build_k3, dim3((n2 + 63) / 64), dim3(64), 0, s, l1, l20, n2, l30, n3, gosper, V, K);
     return hipGetLastError();
 }
 
