@@ -86,6 +86,14 @@ CONFIGS = {
 }
 
 
+def workload(name: str) -> Config:
+    """A standard workload by its name (e.g. "lmax2500_symmetric_n30")."""
+    for c in CONFIGS.values():
+        if c.name == name:
+            return c
+    raise KeyError(name)
+
+
 def small_config(lmax=40, nk=120, nr=20, nmu=None, n1=8, kind="symmetric", seed_index=90,
                  kmin=1e-4, kmax=0.05, r_kind="uniform", k_damp=0.02, l_damp=None,
                  v_power=1.0 / 6.0) -> Config:

@@ -6,7 +6,7 @@ the oracle alone (oracle/ and the seeded input generator; nothing from the
 HIP path) and stored as text: one line per entry, "row col value" with the
 value printed to 17 significant digits.
 
-    python tests/golden/make_oracle_samples.py [config ...]
+    python tests/golden/make_oracle_samples.py [workload name ...]
 """
 import os
 import sys
@@ -20,7 +20,7 @@ sys.path.insert(0, ROOT)
 from oracle import oracle as O                      # noqa: E402
 from paper_1503_08809_amd import synth               # noqa: E402
 
-COUNT = {3: 8, 4: 8, 5: 6}
+COUNT = {"lmax2500_symmetric_n30": 8, "lmax1000_symmetric_n20": 8, "lmax4000_symmetric_n40": 6}
 SEED_OFFSET = 11
 # Besides the seeded entries (almost all small against the largest |Gamma|),
 # entries of the lowest modes, chosen by structure alone: the lowest sorted
@@ -29,30 +29,30 @@ SEED_OFFSET = 11
 STRUCTURAL = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 2)]
 
 
-def path_for(ci: int) -> str:
-    return os.path.join(HERE, f"oracle_gamma_{synth.CONFIGS[ci].name}.txt")
+def path_for(name: str) -> str:
+    return os.path.join(HERE, f"oracle_gamma_{name}.txt")
 
 
-def main(cfgs):
-    for ci in cfgs:
-        cfg = synth.CONFIGS[ci]
+def main(names):
+    for name in names:
+        cfg = synth.workload(name)
         inp = synth.make_inputs(cfg)
         shape = (inp.tri_a.shape[0], inp.tri_p.shape[0])
-        idx = synth.pick_entries(cfg, shape, COUNT[ci], seed_offset=SEED_OFFSET)
+        idx = synth.pick_entries(cfg, shape, COUNT[name], seed_offset=SEED_OFFSET)
         rows, cols = np.unravel_index(idx, shape)
         rows = np.concatenate([rows, [r for r, _ in STRUCTURAL]]).astype(np.int64)
         cols = np.concatenate([cols, [c for _, c in STRUCTURAL]]).astype(np.int64)
         vals = O.gamma_entries(inp, rows, cols)
-        with open(path_for(ci), "w") as f:
+        with open(path_for(name), "w") as f:
             f.write(f"# oracle Gamma entries, workload {cfg.name} (Gamma {shape[0]} x {shape[1]}),\n")
-            f.write(f"# {COUNT[ci]} seeded entries (synth.pick_entries, seed offset {SEED_OFFSET}), then the "
+            f.write(f"# {COUNT[name]} seeded entries (synth.pick_entries, seed offset {SEED_OFFSET}), then the "
                     f"low-mode entries {STRUCTURAL};\n")
             f.write("# written by tests/golden/make_oracle_samples.py from the oracle only\n")
             f.write("# row col value\n")
             for r, c, v in zip(rows, cols, vals):
                 f.write(f"{r} {c} {v:.17g}\n")
-        print("wrote", path_for(ci), flush=True)
+        print("wrote", path_for(name), flush=True)
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [3, 4, 5])
+    main(sys.argv[1:] or list(COUNT))

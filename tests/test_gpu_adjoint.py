@@ -100,7 +100,7 @@ def test_backward_row_tails_vs_oracle(mp, ctx, oracle, prec, n1):
 
 def test_backward_mixed_config2_vs_fp64(mp, ctx):
     """lmax = 500, U = 256 ordered: the mixed adjoint against the FP64 one."""
-    inp = synth.make_inputs(synth.CONFIGS[2])
+    inp = synth.make_inputs(synth.workload("lmax500_ordered_n16"))
     dG = np.random.default_rng(13).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0]))
     pr = mp.projection_from_inputs(ctx, inp)
     G = ctx.to_dev(dG)
@@ -112,7 +112,7 @@ def test_backward_mixed_config2_vs_fp64(mp, ctx):
 
 
 def test_backward_config1_vs_oracle(mp, ctx, oracle):
-    inp = synth.make_inputs(synth.CONFIGS[1])
+    inp = synth.make_inputs(synth.workload("lmax64_ordered_n8"))
     dG = np.random.default_rng(10).standard_normal((512, 512))
     pr = mp.projection_from_inputs(ctx, inp)
     dq, dd = pr.gamma_backward(ctx.to_dev(dG))
@@ -255,7 +255,7 @@ def test_config4_finite_differences_and_mixed(mp, ctx):
     central differences with step 1e-6, and the mixed path's gradient
     against the FP64 one."""
     import torch
-    cfg = synth.CONFIGS[4]
+    cfg = synth.workload("lmax1000_symmetric_n20")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))
@@ -298,7 +298,7 @@ def test_config3_gradient_full_size(mp, ctx):
     = 6 L exactly (Euler).  Also a central difference of the FP64 forward
     along a seeded direction (relative step 1e-4 in every q and Delta entry;
     truncation ~1e-7 relative), and the mixed gradient against the FP64 one."""
-    cfg = synth.CONFIGS[3]
+    cfg = synth.workload("lmax2500_symmetric_n30")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))
@@ -334,7 +334,7 @@ def test_config5_mixed_gradient_euler(mp, ctx):
     """lmax = 4000 stress workload, mixed forward + adjoint with the j_l
     tables regenerated: L = Sum (Gamma * W)^2 is homogeneous of degree 6 in q
     and in Delta, so <dL/dq, q> = <dL/dDelta, Delta> = 6 L."""
-    cfg = synth.CONFIGS[5]
+    cfg = synth.workload("lmax4000_symmetric_n40")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))

@@ -76,7 +76,7 @@ def test_gram_lmax2500_sampled(mp, ctx, oracle):
     """lmax = 2500, 4960 x 4960: sampled <Q, Q> entries (the lowest modes
     among them) against the oracle, FP64 and mixed, and the symmetry of the
     whole matrix."""
-    cfg = synth.CONFIGS[3]
+    cfg = synth.workload("lmax2500_symmetric_n30")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     rows = np.array([0, 0, 1, 2, 100, 1234, 4000, 4959])
@@ -103,7 +103,7 @@ def test_gamma_modal_lmax2500_vs_oracle(mp, ctx, oracle, n1):
     this lmax, and the call then fails with MODAL_ERR_NUMERIC).  FP64:
     backward error with the oracle's <Q, Q> and Gamma' <= 1e-9, forward
     error <= 1e-13 cond(<Q, Q>); mixed: backward error <= 1e-4."""
-    c3 = synth.CONFIGS[3]
+    c3 = synth.workload("lmax2500_symmetric_n30")
     cfg = synth.small_config(lmax=2500, nk=200, nr=4, n1=n1, kind="symmetric",
                              kmin=c3.kmin, kmax=c3.kmax, seed_index=93)
     inp = synth.make_inputs(cfg)

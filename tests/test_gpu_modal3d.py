@@ -97,7 +97,7 @@ def test_3d_lmax1000(mp, ctx):
     Gosper symbol's distance from it."""
     import os
     import torch
-    cfg = synth.CONFIGS[4]
+    cfg = synth.workload("lmax1000_symmetric_n20")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     torch.cuda.synchronize()

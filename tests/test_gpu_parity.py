@@ -179,7 +179,7 @@ def test_gamma_end_to_end_small(mp, ctx, oracle, kind, n1, lmax, nr, nk):
 
 def test_gamma_config1_full(mp, ctx, oracle):
     """lmax = 64, 512 x 512 ordered Gamma: the whole matrix."""
-    inp = synth.make_inputs(synth.CONFIGS[1])
+    inp = synth.make_inputs(synth.workload("lmax64_ordered_n8"))
     pr = mp.projection_from_inputs(ctx, inp)
     g = _np(pr.gamma())
     ref = oracle.gamma_full(inp)
@@ -190,7 +190,7 @@ def test_gamma_config1_full(mp, ctx, oracle):
 
 def test_gamma_config2_sampled(mp, ctx, oracle):
     """lmax = 500, 4096 x 4096 ordered Gamma: seeded sample of entries."""
-    cfg = synth.CONFIGS[2]
+    cfg = synth.workload("lmax500_ordered_n16")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     g = _np(pr.gamma())
@@ -298,7 +298,7 @@ def test_gamma_mixed_small(mp, ctx, oracle, kind, n1, lmax, nr, nk):
 
 
 def test_gamma_mixed_config1_full(mp, ctx, oracle):
-    inp = synth.make_inputs(synth.CONFIGS[1])
+    inp = synth.make_inputs(synth.workload("lmax64_ordered_n8"))
     pr = mp.projection_from_inputs(ctx, inp)
     g = _np(pr.gamma("mixed"))
     ref = oracle.gamma_full(inp)
@@ -311,7 +311,7 @@ def test_gamma_mixed_vs_fp64_config2(mp, ctx, oracle):
     """lmax = 500: the mixed path against the FP64 path (itself pinned to
     the oracle by test_gamma_config2_sampled), and against sampled oracle
     entries."""
-    cfg = synth.CONFIGS[2]
+    cfg = synth.workload("lmax500_ordered_n16")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     g64 = _np(pr.gamma("fp64"))
@@ -357,7 +357,7 @@ FP64_ELEM_BAR = 1e-9
 def test_gamma_config4_sampled(mp, ctx):
     """lmax = 1000, 1540 x 1540 symmetric Gamma: both paths against stored
     oracle entries, and the mixed path against the FP64 path."""
-    cfg = synth.CONFIGS[4]
+    cfg = synth.workload("lmax1000_symmetric_n20")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     g64 = _np(pr.gamma("fp64"))
@@ -379,7 +379,7 @@ def test_gamma_config4_sampled(mp, ctx):
 def test_gamma_config3_sampled(mp, ctx):
     """lmax = 2500, 4960 x 4960 symmetric Gamma: both paths against stored
     oracle entries, and the mixed path against the FP64 path."""
-    cfg = synth.CONFIGS[3]
+    cfg = synth.workload("lmax2500_symmetric_n30")
     inp = synth.make_inputs(cfg)
     pr = mp.projection_from_inputs(ctx, inp)
     g64 = _np(pr.gamma("fp64"))
@@ -400,7 +400,7 @@ def test_gamma_config3_sampled(mp, ctx):
 
 @pytest.fixture(scope="module")
 def config5(mp, ctx):
-    cfg = synth.CONFIGS[5]
+    cfg = synth.workload("lmax4000_symmetric_n40")
     inp = synth.make_inputs(cfg)
     return cfg, inp, mp.projection_from_inputs(ctx, inp)
 

@@ -267,7 +267,7 @@ def test_gamma_vs_bruteforce_config1(oracle):
     """Config lmax=64: the separable mu-quadrature form equals the paper's
     non-separable inner product with exact Wigner symbols (Eq. (3D) with
     exact h^2) to 1e-12 normwise."""
-    inp = synth.make_inputs(synth.CONFIGS[1])
+    inp = synth.make_inputs(synth.workload("lmax64_ordered_n8"))
     g = oracle.gamma_full(inp)
     bf = oracle.brute_force_gamma_ordered(inp)
     err = np.abs(g - bf).max() / np.abs(bf).max()
@@ -413,7 +413,7 @@ def test_stored_samples_come_from_the_oracle(oracle):
     """The stored oracle entries of the lmax = 1000 workload (GPU parity at
     large sizes reads them) agree with the oracle as it stands: two of the
     low-mode entries recomputed (the whole file takes the oracle too long)."""
-    cfg = synth.CONFIGS[4]
+    cfg = synth.workload("lmax1000_symmetric_n20")
     path = os.path.join(GOLDEN, f"oracle_gamma_{cfg.name}.txt")
     a = np.loadtxt(path, comments="#", ndmin=2)
     pick = [i for i in range(a.shape[0]) if (int(a[i, 0]), int(a[i, 1])) in ((0, 0), (1, 1))]

@@ -68,7 +68,7 @@ def test_library_weights_vs_oracle(mp, rule, which):
     if which == "uneven":
         r = _grid(40, seed=2)
     elif which == "clustered":
-        r = synth.r_grid(synth.CONFIGS[3])
+        r = synth.r_grid(synth.workload("lmax2500_symmetric_n30"))
     else:
         r = np.array([1.0, 1.5])
     w = mp.r_weights(rule, r)
