@@ -191,7 +191,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=3, help="workload 1..5")
+    ap.add_argument("--config", type=int, default=3,
+                    help="workload: 1 lmax64_ordered_n8, 2 lmax500_ordered_n16, 3 lmax2500_symmetric_n30, "
+                         "4 lmax1000_symmetric_n20, 5 lmax4000_symmetric_n40")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--forward-only", action="store_true", help="time Gamma without the adjoint")
     ap.add_argument("--no-fp64-ref", action="store_true",

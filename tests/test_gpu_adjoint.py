@@ -98,7 +98,7 @@ def test_backward_row_tails_vs_oracle(mp, ctx, oracle, prec, n1):
     assert eq <= tol and ed <= tol
 
 
-def test_backward_mixed_config2_vs_fp64(mp, ctx):
+def test_backward_mixed_lmax500_vs_fp64(mp, ctx):
     """lmax = 500, U = 256 ordered: the mixed adjoint against the FP64 one."""
     inp = synth.make_inputs(synth.workload("lmax500_ordered_n16"))
     dG = np.random.default_rng(13).standard_normal((inp.tri_a.shape[0], inp.tri_p.shape[0]))
@@ -111,7 +111,7 @@ def test_backward_mixed_config2_vs_fp64(mp, ctx):
     assert eq <= 1e-4 and ed <= 1e-4
 
 
-def test_backward_config1_vs_oracle(mp, ctx, oracle):
+def test_backward_lmax64_vs_oracle(mp, ctx, oracle):
     inp = synth.make_inputs(synth.workload("lmax64_ordered_n8"))
     dG = np.random.default_rng(10).standard_normal((512, 512))
     pr = mp.projection_from_inputs(ctx, inp)
@@ -249,7 +249,7 @@ def test_autograd_reuse_follows_inplace_changes(mp, ctx):
     assert ctx.forward_reuse is False
 
 
-def test_config4_finite_differences_and_mixed(mp, ctx):
+def test_lmax1000_finite_differences_and_mixed(mp, ctx):
     """lmax = 1000, 1540 x 1540 symmetric Gamma, L = Sum (Gamma * W)^2 with W
     a seeded N(0,1) matrix: 32 seeded entries of each gradient against
     central differences with step 1e-6, and the mixed path's gradient
@@ -290,7 +290,7 @@ def test_config4_finite_differences_and_mixed(mp, ctx):
     assert eq <= 1e-4 and ed <= 1e-4
 
 
-def test_config3_gradient_full_size(mp, ctx):
+def test_lmax2500_gradient_full_size(mp, ctx):
     """lmax = 2500, 4960 x 4960 symmetric Gamma, L = Sum (Gamma * W)^2.
 
     Gamma is cubic in q and cubic in Delta (beta is linear in each), so L is
@@ -330,7 +330,7 @@ def test_config3_gradient_full_size(mp, ctx):
     assert eq <= 1e-4 and ed <= 1e-4 and abs(em_q) <= 1e-5
 
 
-def test_config5_mixed_gradient_euler(mp, ctx):
+def test_lmax4000_mixed_gradient_euler(mp, ctx):
     """lmax = 4000 stress workload, mixed forward + adjoint with the j_l
     tables regenerated: L = Sum (Gamma * W)^2 is homogeneous of degree 6 in q
     and in Delta, so <dL/dq, q> = <dL/dDelta, Delta> = 6 L."""

@@ -177,7 +177,7 @@ def test_gamma_end_to_end_small(mp, ctx, oracle, kind, n1, lmax, nr, nk):
     assert np.abs(g - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
-def test_gamma_config1_full(mp, ctx, oracle):
+def test_gamma_lmax64_full(mp, ctx, oracle):
     """lmax = 64, 512 x 512 ordered Gamma: the whole matrix."""
     inp = synth.make_inputs(synth.workload("lmax64_ordered_n8"))
     pr = mp.projection_from_inputs(ctx, inp)
@@ -188,7 +188,7 @@ def test_gamma_config1_full(mp, ctx, oracle):
     assert np.abs(g - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
-def test_gamma_config2_sampled(mp, ctx, oracle):
+def test_gamma_lmax500_sampled(mp, ctx, oracle):
     """lmax = 500, 4096 x 4096 ordered Gamma: seeded sample of entries."""
     cfg = synth.workload("lmax500_ordered_n16")
     inp = synth.make_inputs(cfg)
@@ -297,7 +297,7 @@ def test_gamma_mixed_small(mp, ctx, oracle, kind, n1, lmax, nr, nk):
     assert err <= MIXED_BAR
 
 
-def test_gamma_mixed_config1_full(mp, ctx, oracle):
+def test_gamma_mixed_lmax64_full(mp, ctx, oracle):
     inp = synth.make_inputs(synth.workload("lmax64_ordered_n8"))
     pr = mp.projection_from_inputs(ctx, inp)
     g = _np(pr.gamma("mixed"))
@@ -307,9 +307,9 @@ def test_gamma_mixed_config1_full(mp, ctx, oracle):
     assert err <= MIXED_BAR
 
 
-def test_gamma_mixed_vs_fp64_config2(mp, ctx, oracle):
+def test_gamma_mixed_vs_fp64_lmax500(mp, ctx, oracle):
     """lmax = 500: the mixed path against the FP64 path (itself pinned to
-    the oracle by test_gamma_config2_sampled), and against sampled oracle
+    the oracle by test_gamma_lmax500_sampled), and against sampled oracle
     entries."""
     cfg = synth.workload("lmax500_ordered_n16")
     inp = synth.make_inputs(cfg)
@@ -354,7 +354,7 @@ def _large_entries(g, rows, cols, ref, scale, floor=1e-3):
 FP64_ELEM_BAR = 1e-9
 
 
-def test_gamma_config4_sampled(mp, ctx):
+def test_gamma_lmax1000_sampled(mp, ctx):
     """lmax = 1000, 1540 x 1540 symmetric Gamma: both paths against stored
     oracle entries, and the mixed path against the FP64 path."""
     cfg = synth.workload("lmax1000_symmetric_n20")
@@ -376,7 +376,7 @@ def test_gamma_config4_sampled(mp, ctx):
     assert n64 >= 1 and r64 <= FP64_ELEM_BAR and rm <= MIXED_BAR
 
 
-def test_gamma_config3_sampled(mp, ctx):
+def test_gamma_lmax2500_sampled(mp, ctx):
     """lmax = 2500, 4960 x 4960 symmetric Gamma: both paths against stored
     oracle entries, and the mixed path against the FP64 path."""
     cfg = synth.workload("lmax2500_symmetric_n30")
@@ -399,16 +399,16 @@ def test_gamma_config3_sampled(mp, ctx):
 
 
 @pytest.fixture(scope="module")
-def config5(mp, ctx):
+def lmax4000(mp, ctx):
     cfg = synth.workload("lmax4000_symmetric_n40")
     inp = synth.make_inputs(cfg)
     return cfg, inp, mp.projection_from_inputs(ctx, inp)
 
 
-def test_gamma_config5_mixed_sampled(mp, ctx, config5):
+def test_gamma_lmax4000_mixed_sampled(mp, ctx, lmax4000):
     """lmax = 4000, 11480 x 11480 symmetric Gamma (the stress workload),
     mixed path against stored oracle entries."""
-    cfg, inp, pr = config5
+    cfg, inp, pr = lmax4000
     gm = _np(pr.gamma("mixed"))
     assert gm.shape == (11480, 11480) and np.all(np.isfinite(gm))
     rows, cols, ref = _golden_samples(cfg)

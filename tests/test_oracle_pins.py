@@ -263,7 +263,7 @@ def test_S_mu_parity(oracle):
 
 
 # --------------------------------------------------------------- Gamma
-def test_gamma_vs_bruteforce_config1(oracle):
+def test_gamma_vs_bruteforce_lmax64(oracle):
     """Config lmax=64: the separable mu-quadrature form equals the paper's
     non-separable inner product with exact Wigner symbols (Eq. (3D) with
     exact h^2) to 1e-12 normwise."""
