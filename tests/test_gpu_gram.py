@@ -130,3 +130,15 @@ def test_gamma_modal_rejects_singular_gram(mp, ctx):
     with pytest.raises(mp.ModalError) as e:
         pr.gamma_modal("fp64")
     assert "positive definite" in str(e.value)
+
+
+def test_gram_rejects_too_many_modes(mp, ctx):
+    """na^2 above 8192 late-time pairs is refused before any device work."""
+    inp = synth.make_inputs(synth.small_config(lmax=20, nk=20, nr=2, n1=91, kind="symmetric"), with_delta=False)
+    inp.qk = inp.qk[:2].copy()                      # np = 2: only the Gram's own limit applies
+    inp.tri_a = inp.tri_a[:4].copy()
+    inp.tri_p = np.zeros((1, 3), dtype=np.int32)
+    pr = mp.projection_from_inputs(ctx, inp)
+    with pytest.raises(mp.ModalError) as e:
+        pr.gram("fp64")
+    assert e.value.status == 2 and "na * na" in str(e.value)

@@ -121,3 +121,14 @@ def test_3d_lmax1000(mp, ctx):
     # the Gosper form moves Gamma' by its weighted error (2.3 % at worst per
     # symbol, far less where every L_i is large), not by a dropped factor
     assert 1e-6 < eg < 1e-2
+
+
+def test_3d_rejects_large_moment_tensor(mp, ctx):
+    """np * na above 1280 (a moment tensor over 8 GB) is refused up front."""
+    inp = synth.make_inputs(synth.small_config(lmax=10, nk=20, nr=2, n1=36, kind="symmetric"), with_delta=True)
+    inp.tri_a = inp.tri_a[:4].copy()
+    inp.tri_p = inp.tri_p[:4].copy()
+    pr = mp.projection_from_inputs(ctx, inp)
+    with pytest.raises(mp.ModalError) as e:
+        pr.gamma_3d("exact")
+    assert e.value.status == 2 and "1280" in str(e.value)
