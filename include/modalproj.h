@@ -26,6 +26,13 @@
  *             (Eq. (2D): the six permutation products of the 3x3 block,
  *             i.e. its permanent; repeated indices keep all six terms)
  *
+ * Beside Gamma' it computes the late-time Gram matrix <Q_n, Q_m> and the
+ * full Gamma = <Q, Q>^-1 Gamma' of the Appendix (modal_gram,
+ * modal_gamma_modal), Gamma' by the direct sum over l-triples of Eq. (3D)
+ * with no mu integral (modal_gamma_3d), the adjoint of Gamma'
+ * (modal_gamma_backward) and host-side weights of the r rules
+ * (modal_r_weights).
+ *
  * The mu sum of every r is completed before it enters the r sum (Sec. 2.2).
  * l runs over lmin..lmax (Eq. (3D) starts at l = 2); the arrays indexed
  * by l hold L = lmax - lmin + 1 rows.
@@ -254,7 +261,8 @@ modal_status modal_gamma_modal(modal_ctx ctx, const modal_grid *grid, const moda
  * 2.3 % of the exact symbol for l >= 2), and no mu integral: the form the
  * paper keeps for bases where the separable form is unstable.  With the exact
  * symbol it equals modal_gamma's Gamma' up to rounding.  Same grid and
- * problem as modal_gamma (nmu, mu, wmu unused; both kinds); FP64 throughout.
+ * problem as modal_gamma (mu, wmu unused, nmu only validated as >= 1; both
+ * kinds); FP64 throughout; host or device arrays as everywhere.
  * np * na <= 1280 (the workspace holds the full moment tensor,
  * 8 (np na)^3 bytes, plus about 4 GiB of operands).  gamma: [ta][tp]. */
 modal_status modal_gamma_3d(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
