@@ -132,6 +132,14 @@ def test_gamma_modal_rejects_singular_gram(mp, ctx):
     assert "positive definite" in str(e.value)
 
 
+def test_gram_v_power_zero(mp, ctx, oracle):
+    """v_power = 0: the Gram weights become (2l+1) (no v_l), against the oracle."""
+    inp = synth.make_inputs(synth.small_config(lmax=22, nk=30, nr=3, n1=4, kind="symmetric", seed_index=101,
+                                               v_power=0.0))
+    pr = mp.projection_from_inputs(ctx, inp)
+    assert normwise(_np(pr.gram("fp64")), oracle.gram_full(inp)) <= 1e-10
+
+
 def test_gram_rejects_too_many_modes(mp, ctx):
     """na^2 above 8192 late-time pairs is refused before any device work."""
     inp = synth.make_inputs(synth.small_config(lmax=20, nk=20, nr=2, n1=91, kind="symmetric"), with_delta=False)

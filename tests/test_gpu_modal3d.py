@@ -58,6 +58,14 @@ def test_3d_vs_oracle(mp, ctx, oracle, threej, kind, n1, lmax, nr, nk):
     assert err <= 1e-12
 
 
+def test_3d_v_power_zero(mp, ctx, oracle):
+    """v_power = 0 (weights (2l+1) / sqrt(C_l)): Eq. (3D) against the oracle."""
+    inp = synth.make_inputs(synth.small_config(lmax=22, nk=40, nr=4, n1=3, kind="symmetric", seed_index=100,
+                                               v_power=0.0))
+    pr = mp.projection_from_inputs(ctx, inp)
+    assert normwise(_np(pr.gamma_3d("exact")), oracle.gamma_3d(inp)) <= 1e-12
+
+
 @pytest.mark.parametrize("l", [2, 3])
 def test_3d_single_l(mp, ctx, oracle, l):
     """One multipole (lmin = lmax = l): for even l the single triple (l, l, l)
