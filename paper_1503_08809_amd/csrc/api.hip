@@ -643,7 +643,9 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
     double *Ab = (double *)ws_get(c, W_A3, per_r * nrb);
     double *Bb = (double *)ws_get(c, W_B3, sizeof(double) * (size_t)U * U * nrb);
     double *Cb = (double *)ws_get(c, W_C3, sizeof(double) * (size_t)U * nrb);
-    double *Kb = (double *)ws_get(c, W_K3, sizeof(double) * std::max<size_t>(1, (size_t)std::max(nE, nO) * std::max(nE, nO)));
+    // the symbol blocks of both parity classes of l2 for one l1
+    const size_t kblk = std::max<size_t>(1, (size_t)std::max(nE, nO) * std::max(nE, nO));
+    double *Kb = (double *)ws_get(c, W_K3, sizeof(double) * 2 * kblk);
     // T(u1, u2 <= u3) only (T is symmetric in its last two indices), the
     // (u2, u3) pairs packed column by column: NT = U (U + 1) / 2 columns
     const int NT = U * (U + 1) / 2;
@@ -662,6 +664,8 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
               "Eq. (3D) operand");
         for (int l1 = g->lmin; l1 <= g->lmax; ++l1) {
             const int p1 = l1 & 1;
+            hipck(c, launch_build_k3(l1, l0c, nc, threej == MODAL_3J_GOSPER, V, Kb, Kb + kblk, c->stream),
+                  "Eq. (3D) symbols");
             for (int par2 = 0; par2 < 2; ++par2) {
                 // class 0 = even l, 1 = odd l; l3 has the parity of l1 + l2
                 const int par3 = (p1 + par2) & 1;
@@ -671,8 +675,7 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
                     hipck(c, launch_zero_rows3(L, offc[par2], n2, (int64_t)nb * U, Ab, c->stream), "Eq. (3D) empty rows");
                     continue;
                 }
-                hipck(c, launch_build_k3(l1, l0c[par2], n2, l0c[par3], n3, threej == MODAL_3J_GOSPER, V, Kb, c->stream),
-                      "Eq. (3D) symbols");
+                const double *Kp = Kb + (par2 ? kblk : 0);
                 // rows in chunks, each multiplied only over the l3 columns its
                 // triangles reach: |l1 - l2| <= l3 <= l1 + l2 (half the block
                 // on average)
@@ -689,7 +692,7 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
                         continue;
                     }
                     blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, i2b - i2a, nb * U,
-                                             c1 - c0 + 1, &one, Kb + (size_t)c0 * n2 + i2a, n2,
+                                             c1 - c0 + 1, &one, Kp + (size_t)c0 * n2 + i2a, n2,
                                              Gb + offc[par3] + c0, L, &nil, Ab + offc[par2] + i2a, L),
                             "Eq. (3D) stage 1");
                 }

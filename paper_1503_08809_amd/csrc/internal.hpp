@@ -184,8 +184,8 @@ hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const doub
 hipError_t launch_build_g3(int L, int nE, int lE0, int lO0, int lmin, int nr, int np, int na, int r0, int nrb,
                            const double *wl, const double *ql, const double *beta, double *G, hipStream_t s);
 hipError_t launch_start3(int lmax, double *V, hipStream_t s);
-hipError_t launch_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper, const double *V, double *K,
-                           hipStream_t s);
+hipError_t launch_build_k3(int l1, const int l0[2], const int n[2], int gosper, const double *V, double *K0,
+                           double *K1, hipStream_t s);
 hipError_t launch_c3(int L, int lp1, int U, int r0, int nrb, const double *r, const double *wr, const double *G,
                      double *C, hipStream_t s);
 hipError_t launch_pack3(int U, int nrb, const double *B, double *P, hipStream_t s);

@@ -89,14 +89,27 @@ __device__ __forceinline__ double threej_sq_gosper(int l1, int l2, int l3)
 }
 
 // K[i3 * n2 + i2] = 2 (l1 l2 l3; 000)^2 with l2 = l20 + 2 i2, l3 = l30 + 2 i3
-// (l20, l30 of the two parity classes, l1 + l2 + l3 even); zero outside
+// (l20, l30 of two parity classes with l1 + l2 + l3 even); zero outside
 // the triangle |l1 - l2| <= l3 <= l1 + l2.  One thread per l2 walks l3 upward
 // from |l1 - l2| with the step ratio (exact) or evaluates the Gosper form.
-__global__ void k_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper, const double *__restrict__ V,
-                           double *__restrict__ K)
+// Both parity classes of l2 in one launch: blockIdx.y is the class of l2
+// (0 even, 1 odd), K[class] its block.
+struct K3Args {
+    int l1, gosper;
+    int l0[2], n[2];          // first l and count of each parity class
+    const double *V;
+    double *K[2];
+};
+
+__global__ void k_build_k3(K3Args a)
 {
+    const int c2 = blockIdx.y, c3 = (a.l1 & 1) ^ c2;
+    const int n2 = a.n[c2], n3 = a.n[c3];
     const int i2 = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i2 >= n2) return;
+    if (i2 >= n2 || n3 == 0) return;
+    const int l1 = a.l1, l20 = a.l0[c2], l30 = a.l0[c3], gosper = a.gosper;
+    const double *__restrict__ V = a.V;
+    double *__restrict__ K = a.K[c2];
     const int l2 = l20 + 2 * i2;
     const int lo = abs(l1 - l2), hi = l1 + l2;
     int lc = lo;
@@ -195,11 +208,13 @@ hipError_t launch_start3(int lmax, double *V, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_build_k3(int l1, int l20, int n2, int l30, int n3, int gosper, const double *V, double *K,
-                           hipStream_t s)
+hipError_t launch_build_k3(int l1, const int l0[2], const int n[2], int gosper, const double *V, double *K0,
+                           double *K1, hipStream_t s)
 {
-    if (n2 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_k3, dim3((n2 + 63) / 64), dim3(64), 0, s, l1, l20, n2, l30, n3, gosper, V, K);
+    const int nmax = std::max(n[0], n[1]);
+    if (nmax <= 0) return hipSuccess;
+    K3Args a{l1, gosper, {l0[0], l0[1]}, {n[0], n[1]}, V, {K0, K1}};
+    hipLaunchKernelGGL(k_build_k3, dim3((nmax + 63) / 64, 2), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
