@@ -613,6 +613,7 @@ void blas_bind(modal_ctx c)
 // then gathered.  The r axis is taken in batches so that the G and A
 // operands stay within about 2 GiB each.
 constexpr int kRowChunk3d = 128;
+constexpr int kU2Block3d = 128;
 
 void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, const Dims &d, int threej,
                   double *gamma)
@@ -646,8 +647,8 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
     // the symbol blocks of both parity classes of l2 for one l1
     const size_t kblk = std::max<size_t>(1, (size_t)std::max(nE, nO) * std::max(nE, nO));
     double *Kb = (double *)ws_get(c, W_K3, sizeof(double) * 2 * kblk);
-    // T(u1, u2 <= u3) only (T is symmetric in its last two indices), the
-    // (u2, u3) pairs packed column by column: NT = U (U + 1) / 2 columns
+    // T over the (u2 <= u3) pairs, packed u2-major: NT = U (U + 1) / 2
+    // columns, of which only the rows u1 <= u2 are formed and read
     const int NT = U * (U + 1) / 2;
     double *Pb = (double *)ws_get(c, W_P3, sizeof(double) * (size_t)NT * nrb);
     const size_t tn = (size_t)U * NT;
@@ -718,9 +719,16 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
             hipck(c, launch_pack3(U, nb, Bb, Pb, c->stream), "Eq. (3D) pack");
             const int lp1 = p1 == 0 ? (l1 - lE0) / 2 : nE + (l1 - lO0) / 2;
             hipck(c, launch_c3(L, lp1, U, r0, nb, G.r, G.wr, Gb, Cb, c->stream), "Eq. (3D) radial weights");
-            blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, U, NT, nb, &one, Cb,
-                                     U, Pb, NT, &one, T, U),
-                    "Eq. (3D) stage 3");
+            // T(u1, (u2, u3)) for u1 below the end of the u2 block: u1 <= u2 <= u3
+            // is all the gather reads
+            for (int b0 = 0; b0 < U; b0 += kU2Block3d) {
+                const int b1 = std::min(U, b0 + kU2Block3d);
+                const int64_t t0 = (int64_t)b0 * U - (int64_t)b0 * (b0 - 1) / 2;
+                const int64_t t1 = (int64_t)b1 * U - (int64_t)b1 * (b1 - 1) / 2;
+                blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, b1,
+                                         (int)(t1 - t0), nb, &one, Cb, U, Pb + t0, NT, &one, T + (size_t)t0 * U, U),
+                        "Eq. (3D) stage 3");
+            }
         }
     }
     const int *ta = dev_in(c, p->tri_a, (size_t)p->ta * 3);

@@ -179,8 +179,8 @@ hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const doub
 // Eq. (3D) (k_modal3d.hip): operand G[(rb U + u) L + l'] (l' parity-sorted,
 // even l first) for r in [r0, r0 + nrb); the band of 2 (3j)^2 for one l1 and
 // one pair of parity classes, K[i3 n2 + i2]; the r weights times the row l1'
-// of G, C[rb U + u]; the packing of the upper triangles of B_r; and the
-// gather of Gamma' from T[u1 + U (u3 (u3 + 1) / 2 + u2)], u2 <= u3.
+// of G, C[rb U + u]; the packing of the upper triangles of B_r (u2-major
+// pairs); and the gather of Gamma' from T(u1 <= u2 <= u3).
 hipError_t launch_build_g3(int L, int nE, int lE0, int lO0, int lmin, int nr, int np, int na, int r0, int nrb,
                            const double *wl, const double *ql, const double *beta, double *G, hipStream_t s);
 hipError_t launch_start3(int lmax, double *V, hipStream_t s);

@@ -15,8 +15,9 @@
 //   A_r(l2, u3) = Sum_l3 K(l1, l2, l3) G_u3(l3, r)          (stage 1)
 //   B_r(u2, u3) = Sum_l2 G_u2(l2, r) A_r(l2, u3)            (stage 2)
 //   T(u1, u2, u3) += Sum_r wr r^2 G_u1(l1, r) B_r(u2, u3)   (stage 3)
-// B_r and T are symmetric in (u2, u3): stage 2 forms one triangle, which is
-// packed, and stage 3 and T run over the packed pairs only.
+// B_r is symmetric in (u2, u3) and T in all three: stage 2 forms one
+// triangle of B_r, packed u2-major, and stage 3 forms T only for rows
+// u1 below the end of each 128-wide block of u2 (u1 <= u2 <= u3 is read).
 // The l index is stored parity-sorted (even l first): for a given l1, K is
 // non-zero only where l1 + l2 + l3 is even, so stage 1 is two dense products
 // of half size (one per parity of l2).  The three stages are plain GEMMs
@@ -144,7 +145,14 @@ __global__ void k_c3(int L, int lp1, int U, int r0, int nrb, const double *__res
     C[i] = wr[r0 + rb] * x * x * G[(size_t)i * L + lp1];
 }
 
-// P[rb NT + u3 (u3 + 1) / 2 + u2] = B[rb U^2 + u2 + U u3] for u2 <= u3.
+// Packed pair index of (u2 <= u3), u2-major: the pairs of one u2 are
+// contiguous, from u2 U - u2 (u2 - 1) / 2.
+__device__ __forceinline__ int64_t pair3(int U, int u2, int u3)
+{
+    return (int64_t)u2 * U - (int64_t)u2 * (u2 - 1) / 2 + (u3 - u2);
+}
+
+// P[rb NT + pair3(u2, u3)] = B[rb U^2 + u2 + U u3] for u2 <= u3.
 __global__ void k_pack3(int U, int nrb, const double *__restrict__ B, double *__restrict__ P)
 {
     const int64_t n = (int64_t)U * U * nrb;
@@ -153,7 +161,7 @@ __global__ void k_pack3(int U, int nrb, const double *__restrict__ B, double *__
         const int u2 = (int)(i % U);
         const int64_t rest = i / U;
         const int u3 = (int)(rest % U), rb = (int)(rest / U);
-        if (u2 <= u3) P[rb * NT + (int64_t)u3 * (u3 + 1) / 2 + u2] = B[i];
+        if (u2 <= u3) P[rb * NT + pair3(U, u2, u3)] = B[i];
     }
 }
 
@@ -166,8 +174,8 @@ __global__ void k_zero_rows3(int64_t ld, int row0, int nrows, int64_t ncols, dou
         A[(i / nrows) * ld + row0 + i % nrows] = 0.0;
 }
 
-// Gamma[n][m] from T(u1, u2, u3), symmetric, stored for u2 <= u3 as
-// T[u1 + U (u3 (u3 + 1) / 2 + u2)].
+// Gamma[n][m] from T(u1, u2, u3), fully symmetric, held for u1 <= u2 <= u3
+// at T[u1 + U pair3(u2, u3)].
 __global__ void k_gather3(int kind, int ta, int tp, const int *__restrict__ tri_a, const int *__restrict__ tri_p,
                           int np, int U, const double *__restrict__ T, double *__restrict__ gamma)
 {
@@ -177,9 +185,11 @@ __global__ void k_gather3(int kind, int ta, int tp, const int *__restrict__ tri_
     const int a0 = tri_a[3 * n] * np, a1 = tri_a[3 * n + 1] * np, a2 = tri_a[3 * n + 2] * np;
     const int p0 = tri_p[3 * m], p1 = tri_p[3 * m + 1], p2 = tri_p[3 * m + 2];
     auto at = [&](int x, int y, int z) {
-        const int v = a1 + y, w = a2 + z;
-        const int lo = min(v, w), hi = max(v, w);
-        return T[(size_t)(a0 + x) + (size_t)U * ((size_t)hi * (hi + 1) / 2 + lo)];
+        int s0 = a0 + x, s1 = a1 + y, s2 = a2 + z, t;
+        if (s0 > s1) { t = s0; s0 = s1; s1 = t; }
+        if (s1 > s2) { t = s1; s1 = s2; s2 = t; }
+        if (s0 > s1) { t = s0; s0 = s1; s1 = t; }
+        return T[(size_t)s0 + (size_t)U * pair3(U, s1, s2)];
     };
     if (kind == MODAL_GAMMA_ORDERED) {
         gamma[i] = at(p0, p1, p2) / (8.0 * kPi);
