@@ -700,9 +700,11 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
             }
             // B_r = G_r^T K G_r is symmetric (K is symmetric in l2, l3): of
             // its 2 x 2 blocks only the three on or above the diagonal, then
-            // the upper triangle packed column by column
+            // the upper triangle packed (u2-major pairs)
             {
-                const int h = (U + 1) / 2;
+                // the split on a multiple of 64 (the GEMM's tile edge), so
+                // that fewer tiles straddle a block edge
+                const int h = std::min(U, pad_to((U + 1) / 2, 64));
                 const int off[3][2] = {{0, 0}, {0, h}, {h, h}};
                 for (int b = 0; b < 3; ++b) {
                     const int u0 = off[b][0], v0 = off[b][1];
