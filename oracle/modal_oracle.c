@@ -281,40 +281,54 @@ int or_S(int lmin, int lmax, const double *cl, double v_power, int na, const dou
 /*   kind 1 (symmetric): F = permanent of [S_{a_s p_t}],  c = 1/(48 pi)  */
 /* Gamma_e = c Sum_r wr_r r^2 [ Sum_mu wmu_mu F(r, mu) ]: the mu sum is  */
 /* completed for each r before the r sum (Sec. 2.2).                     */
+/* If scale is not NULL, scale_e receives the same sums taken over the   */
+/* absolute values of every product term of F and of the weights,        */
+/*   c Sum_r |wr_r| r^2 Sum_mu |wmu_mu| Sum_terms |S S S|,                */
+/* the size of the summands behind Gamma_e: any summation order (and any */
+/* relative perturbation d of each term) moves Gamma_e by at most about  */
+/* d scale_e, so it is the yardstick for an elementwise comparison.      */
 /* ------------------------------------------------------------------ */
 int or_gamma_entries(int kind, int nr, const double *r, const double *wr,
                      int nmu, const double *wmu, int nS, const double *S,
-                     int64_t ne, const int32_t *sidx, double *gamma)
+                     int64_t ne, const int32_t *sidx, double *gamma, double *scale)
 {
     for (int64_t e = 0; e < 9 * ne; ++e) if (sidx[e] < 0 || sidx[e] >= nS) return -1;
     double c = (kind == 0) ? 1.0 / (8.0 * OR_PI) : 1.0 / (48.0 * OR_PI);
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t e = 0; e < ne; ++e) {
         const int32_t *ix = sidx + 9 * e;
-        double outer = 0.0;
+        double outer = 0.0, outer_abs = 0.0;
         for (int q = 0; q < nr; ++q) {
             const double *m[3][3];
             for (int s = 0; s < 3; ++s)
                 for (int t = 0; t < 3; ++t)
                     m[s][t] = S + ((size_t)ix[3 * s + t] * nr + q) * nmu;
-            double inner = 0.0;
+            double inner = 0.0, inner_abs = 0.0;
             for (int j = 0; j < nmu; ++j) {
-                double F;
+                double F, Fabs;
                 if (kind == 0) {
                     F = m[0][0][j] * m[1][1][j] * m[2][2][j];
+                    Fabs = fabs(F);
                 } else {
-                    F = m[0][0][j] * m[1][1][j] * m[2][2][j]
-                      + m[0][0][j] * m[1][2][j] * m[2][1][j]
-                      + m[0][1][j] * m[1][0][j] * m[2][2][j]
-                      + m[0][1][j] * m[1][2][j] * m[2][0][j]
-                      + m[0][2][j] * m[1][0][j] * m[2][1][j]
-                      + m[0][2][j] * m[1][1][j] * m[2][0][j];
+                    double t6[6];
+                    t6[0] = m[0][0][j] * m[1][1][j] * m[2][2][j];
+                    t6[1] = m[0][0][j] * m[1][2][j] * m[2][1][j];
+                    t6[2] = m[0][1][j] * m[1][0][j] * m[2][2][j];
+                    t6[3] = m[0][1][j] * m[1][2][j] * m[2][0][j];
+                    t6[4] = m[0][2][j] * m[1][0][j] * m[2][1][j];
+                    t6[5] = m[0][2][j] * m[1][1][j] * m[2][0][j];
+                    F = t6[0] + t6[1] + t6[2] + t6[3] + t6[4] + t6[5];
+                    Fabs = fabs(t6[0]) + fabs(t6[1]) + fabs(t6[2]) + fabs(t6[3]) + fabs(t6[4])
+                         + fabs(t6[5]);
                 }
                 inner += wmu[j] * F;
+                inner_abs += fabs(wmu[j]) * Fabs;
             }
             outer += wr[q] * r[q] * r[q] * inner;
+            outer_abs += fabs(wr[q]) * r[q] * r[q] * inner_abs;
         }
         gamma[e] = c * outer;
+        if (scale) scale[e] = c * outer_abs;
     }
     return 0;
 }

@@ -52,7 +52,7 @@ def lib():
         L.or_S.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, _dp,
                            ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_int, _ip, _dp]
         L.or_gamma_entries.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
-                                       ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp]
+                                       ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp, _dp]
         L.or_gamma_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
                                        ctypes.c_int, _dp, ctypes.c_int64, _ip, _dp, _dp]
         L.or_S_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int,
@@ -151,8 +151,12 @@ def _kind_code(kind: str) -> int:
     return 0 if kind == "ordered" else 1
 
 
-def gamma_from_S(inp, wmu, S_arr, sidx) -> np.ndarray:
-    """Gamma entries from an S stack and per-entry 3x3 index blocks (Eq. (2D))."""
+def gamma_from_S(inp, wmu, S_arr, sidx, return_scale=False):
+    """Gamma entries from an S stack and per-entry 3x3 index blocks (Eq. (2D)).
+
+    With return_scale, also the per-entry magnitude scale
+    c Sum_r wr r^2 Sum_mu wmu Sum_terms |S S S| (the same sums over absolute
+    values of every product term): the yardstick of an elementwise check."""
     c = inp.cfg
     S_arr, sp_ = _d(S_arr)
     sidx, sip = _i(np.asarray(sidx).reshape(-1, 9))
@@ -160,16 +164,20 @@ def gamma_from_S(inp, wmu, S_arr, sidx) -> np.ndarray:
     wr, wrp = _d(inp.wr)
     wmu, wmp = _d(wmu)
     out = np.empty(sidx.shape[0])
+    scale = np.empty(sidx.shape[0]) if return_scale else None
     _check(lib().or_gamma_entries(_kind_code(c.kind), c.nr, rp, wrp, wmu.size, wmp,
                                   S_arr.shape[0], sp_, sidx.shape[0], sip,
-                                  out.ctypes.data_as(_dp)), "gamma")
-    return out
+                                  out.ctypes.data_as(_dp),
+                                  scale.ctypes.data_as(_dp) if return_scale else None), "gamma")
+    return (out, scale) if return_scale else out
 
 
-def gamma_entries(inp, rows, cols, mu=None, wmu=None, return_S=False):
+def gamma_entries(inp, rows, cols, mu=None, wmu=None, return_S=False, return_scale=False):
     """Gamma[tri_a[rows[e]], tri_p[cols[e]]] computed one entry at a time.
 
     Only the beta rows and S pairs the requested entries touch are formed.
+    With return_scale the result is (values, scales), scales as in
+    gamma_from_S; with return_S, (result, S stack, {(a, p): stack index}).
     """
     c = inp.cfg
     if mu is None:
@@ -193,7 +201,7 @@ def gamma_entries(inp, rows, cols, mu=None, wmu=None, return_S=False):
         for s in range(3):
             for t in range(3):
                 sidx[e, 3 * s + t] = need[(int(ta[e, s]), int(tp[e, t]))]
-    g = gamma_from_S(inp, wmu, S_arr, sidx)
+    g = gamma_from_S(inp, wmu, S_arr, sidx, return_scale=return_scale)
     if return_S:
         return g, S_arr, need
     return g

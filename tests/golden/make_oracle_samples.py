@@ -1,15 +1,30 @@
-"""Write oracle values of sampled Gamma entries at the large workloads.
+"""Write oracle values of whole Gamma rows at the large workloads.
 
-Gamma entries at lmax = 1000, 2500 and 4000 take the oracle seconds to minutes to
-compute, too long for a GPU test run, so they are computed here, once, by
-the oracle alone (oracle/ and the seeded input generator; nothing from the
-HIP path) and stored as text: one line per entry, "row col value" with the
-value printed to 17 significant digits.
+Gamma at lmax = 500, 1000, 2500 and 4000 takes the oracle minutes to hours
+to compute, too long for a GPU test run, so whole rows of it are computed
+here, once, by the oracle alone (oracle/ and the seeded input generator;
+nothing from the HIP path) and stored as gzipped text, one line per entry:
+
+    row col value scale
+
+value is Gamma[row, col] and scale is the oracle's magnitude scale of that
+entry, c Sum_r wr r^2 Sum_mu wmu Sum_terms |S S S| (Eq. (2D) taken over the
+absolute values of its product terms): an elementwise check compares
+|Gamma - value| with a tolerance times scale, which is well posed for
+entries that cancel to nearly zero as well as for the largest ones.
+
+Rows: every column (every p-triple) of six a-triples chosen by structure,
+the lowest modes (0,0,0), (0,0,1), a triple of three distinct low modes,
+one seeded row, three distinct high modes (N1-3, N1-2, N1-1) and the
+highest (N1-1, N1-1, N1-1); for the ordered lists the distinct low triple
+is (2, 1, 0), whose order differs from the sorted one.
 
     python tests/golden/make_oracle_samples.py [workload name ...]
 """
+import gzip
 import os
 import sys
+import time
 
 import numpy as np
 
@@ -20,39 +35,55 @@ sys.path.insert(0, ROOT)
 from oracle import oracle as O                      # noqa: E402
 from paper_1503_08809_amd import synth               # noqa: E402
 
-COUNT = {"lmax2500_symmetric_n30": 8, "lmax1000_symmetric_n20": 8, "lmax4000_symmetric_n40": 6}
+WORKLOADS = ["lmax500_ordered_n16", "lmax1000_symmetric_n20", "lmax2500_symmetric_n30",
+             "lmax4000_symmetric_n40"]
 SEED_OFFSET = 11
-# Besides the seeded entries (almost all small against the largest |Gamma|),
-# entries of the lowest modes, chosen by structure alone: the lowest sorted
-# triples carry the most power, so these sit near the top of |Gamma| and pin
-# the large entries elementwise.
-STRUCTURAL = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 2)]
 
 
 def path_for(name: str) -> str:
-    return os.path.join(HERE, f"oracle_gamma_{name}.txt")
+    return os.path.join(HERE, f"oracle_rows_{name}.txt.gz")
+
+
+def row_of(tri: np.ndarray, t) -> int:
+    hit = np.nonzero((tri == np.asarray(t, dtype=tri.dtype)).all(axis=1))[0]
+    if hit.size != 1:
+        raise ValueError(f"triple {t} not in the mode list")
+    return int(hit[0])
+
+
+def chosen_rows(cfg, tri: np.ndarray):
+    n = cfg.n1
+    low3 = (2, 1, 0) if cfg.kind == "ordered" else (0, 1, 2)
+    fixed = [row_of(tri, t) for t in [(0, 0, 0), (0, 0, 1), low3, (n - 3, n - 2, n - 1),
+                                      (n - 1, n - 1, n - 1)]]
+    rng = np.random.Generator(np.random.PCG64(cfg.pick_seed + SEED_OFFSET))
+    while True:
+        seeded = int(rng.integers(0, tri.shape[0]))
+        if seeded not in fixed:
+            break
+    return sorted(fixed + [seeded])
 
 
 def main(names):
     for name in names:
+        t0 = time.time()
         cfg = synth.workload(name)
         inp = synth.make_inputs(cfg)
-        shape = (inp.tri_a.shape[0], inp.tri_p.shape[0])
-        idx = synth.pick_entries(cfg, shape, COUNT[name], seed_offset=SEED_OFFSET)
-        rows, cols = np.unravel_index(idx, shape)
-        rows = np.concatenate([rows, [r for r, _ in STRUCTURAL]]).astype(np.int64)
-        cols = np.concatenate([cols, [c for _, c in STRUCTURAL]]).astype(np.int64)
-        vals = O.gamma_entries(inp, rows, cols)
-        with open(path_for(name), "w") as f:
-            f.write(f"# oracle Gamma entries, workload {cfg.name} (Gamma {shape[0]} x {shape[1]}),\n")
-            f.write(f"# {COUNT[name]} seeded entries (synth.pick_entries, seed offset {SEED_OFFSET}), then the "
-                    f"low-mode entries {STRUCTURAL};\n")
+        ta, tp = inp.tri_a.shape[0], inp.tri_p.shape[0]
+        rows_sel = chosen_rows(cfg, inp.tri_a)
+        rows = np.repeat(np.asarray(rows_sel, dtype=np.int64), tp)
+        cols = np.tile(np.arange(tp, dtype=np.int64), len(rows_sel))
+        vals, scale = O.gamma_entries(inp, rows, cols, return_scale=True)
+        with gzip.open(path_for(name), "wt") as f:
+            f.write(f"# oracle Gamma rows, workload {cfg.name} (Gamma {ta} x {tp}),\n")
+            f.write(f"# rows {rows_sel} (a-triples {[tuple(int(v) for v in inp.tri_a[r]) for r in rows_sel]}),"
+                    f" every column\n")
             f.write("# written by tests/golden/make_oracle_samples.py from the oracle only\n")
-            f.write("# row col value\n")
-            for r, c, v in zip(rows, cols, vals):
-                f.write(f"{r} {c} {v:.17g}\n")
-        print("wrote", path_for(name), flush=True)
+            f.write("# row col value scale (scale = c Sum_r wr r^2 Sum_mu wmu Sum_terms |S S S|)\n")
+            for r, c, v, s in zip(rows, cols, vals, scale):
+                f.write(f"{r} {c} {v:.17g} {s:.17g}\n")
+        print(f"wrote {path_for(name)} ({rows.size} entries, {time.time() - t0:.0f} s)", flush=True)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(COUNT))
+    main(sys.argv[1:] or WORKLOADS)

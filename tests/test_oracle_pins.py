@@ -6,6 +6,7 @@ closed form, an exact rational value, an independent library routine
 non-separable definition, or an invariant of the method.
 """
 import math
+import dataclasses
 import os
 
 import numpy as np
@@ -409,15 +410,72 @@ def test_inputs_deterministic():
     assert abs(a.wk.sum() - (a.k[-1] - a.k[0])) < 1e-14
 
 
-def test_stored_samples_come_from_the_oracle(oracle):
-    """The stored oracle entries of the lmax = 1000 workload (GPU parity at
-    large sizes reads them) agree with the oracle as it stands: two of the
-    low-mode entries recomputed (the whole file takes the oracle too long)."""
+def test_stored_rows_come_from_the_oracle(oracle):
+    """The stored oracle rows of the lmax = 1000 workload (GPU parity at large
+    sizes reads them) agree with the oracle as it stands: three entries,
+    values and magnitude scales, recomputed (the whole file takes the oracle
+    too long)."""
+    import stored_rows
     cfg = synth.workload("lmax1000_symmetric_n20")
-    path = os.path.join(GOLDEN, f"oracle_gamma_{cfg.name}.txt")
-    a = np.loadtxt(path, comments="#", ndmin=2)
-    pick = [i for i in range(a.shape[0]) if (int(a[i, 0]), int(a[i, 1])) in ((0, 0), (1, 1))]
-    assert len(pick) == 2
+    rows, cols, ref, scale = stored_rows.load(cfg.name)
+    assert np.unique(rows).size == 6 and rows.size == 6 * 1540
+    pick = [0, rows.size // 2 + 17, rows.size - 1]
     inp = synth.make_inputs(cfg)
-    v = oracle.gamma_entries(inp, a[pick, 0].astype(np.int64), a[pick, 1].astype(np.int64))
-    np.testing.assert_allclose(v, a[pick, 2], rtol=1e-12, atol=0)
+    v, sc = oracle.gamma_entries(inp, rows[pick], cols[pick], return_scale=True)
+    np.testing.assert_allclose(v, ref[pick], rtol=1e-15, atol=0)
+    np.testing.assert_allclose(sc, scale[pick], rtol=1e-15, atol=0)
+
+
+def test_entry_scale_bounds_the_entry(oracle):
+    """The magnitude scale is the same sum over absolute values: it bounds
+    |Gamma| and equals it when every product term has one sign (ordered
+    Gamma with S > 0), and it is linear in each S row's magnitude."""
+    inp = synth.make_inputs(synth.small_config(lmax=24, nk=60, nr=5, n1=4, kind="symmetric"))
+    mu, wmu = oracle.gauss_legendre(inp.cfg.nmu)
+    S, _ = oracle.full_S(inp, mu)
+    S = S.reshape(-1, inp.cfg.nr, mu.size)
+    n = 40
+    rng = np.random.default_rng(5)
+    sidx = rng.integers(0, S.shape[0], size=(n, 9)).astype(np.int32)
+    g, sc = oracle.gamma_from_S(inp, wmu, S, sidx, return_scale=True)
+    assert np.all(sc >= np.abs(g)) and np.all(sc > 0)
+    # all terms positive: the scale is the value itself
+    cfg_o = dataclasses.replace(inp.cfg, kind="ordered")
+    inp_o = dataclasses.replace(inp, cfg=cfg_o)
+    g2, sc2 = oracle.gamma_from_S(inp_o, wmu, np.abs(S), sidx, return_scale=True)
+    np.testing.assert_allclose(sc2, g2, rtol=1e-14)
+    # flipping the sign of S leaves the scale unchanged and negates Gamma
+    g3, sc3 = oracle.gamma_from_S(inp, wmu, -S, sidx, return_scale=True)
+    np.testing.assert_allclose(g3, -g, rtol=1e-14)
+    np.testing.assert_allclose(sc3, sc, rtol=1e-14)
+
+
+def test_stored_rows_detect_a_perturbed_S_row(oracle):
+    """The elementwise check against stored rows catches a wrong S row: at
+    lmax = 500 (ordered), 64 stored entries of the row a = (2, 1, 0) that use
+    the pair (a = 1, p = 3) are recomputed by the oracle with that S row
+    unchanged (equal to the stored values), zeroed, scaled by 1 + 1e-3
+    (both fail the mixed bar) and scaled by 1 + 1e-7 (fails the FP64 bar).
+    The perturbation is planted in the oracle's S, on the CPU."""
+    import stored_rows
+    cfg = synth.workload("lmax500_ordered_n16")
+    rows, cols, ref, scale = stored_rows.load(cfg.name)
+    inp = synth.make_inputs(cfg)
+    r210 = 2 * 256 + 1 * 16 + 0
+    sel = np.nonzero((rows == r210) & (inp.tri_p[cols][:, 1] == 3))[0][:64]
+    assert sel.size == 64
+    mu, wmu = oracle.gauss_legendre(cfg.nmu)
+    g, S, need = oracle.gamma_entries(inp, rows[sel], cols[sel], mu, wmu, return_S=True)
+    assert stored_rows.worst(g, ref[sel], scale[sel]) <= 1e-14
+    # the 3x3 index blocks of these entries, as gamma_entries forms them
+    ta, tp = inp.tri_a[rows[sel]], inp.tri_p[cols[sel]]
+    pos = {p: i for i, p in enumerate(np.unique(tp))}
+    sidx = np.array([[need[(int(ta[e, s]), pos[int(tp[e, t])])] for s in range(3) for t in range(3)]
+                     for e in range(sel.size)], dtype=np.int32)
+    k = need[(1, pos[3])]
+    for factor, bar in ((0.0, stored_rows.MIXED_TOL), (1 + 1e-3, stored_rows.MIXED_TOL),
+                        (1 + 1e-7, stored_rows.FP64_TOL)):
+        Sp = S.copy()
+        Sp[k] *= factor
+        gp = oracle.gamma_from_S(inp, wmu, Sp, sidx)
+        assert stored_rows.worst(gp, ref[sel], scale[sel]) > bar, factor
