@@ -183,6 +183,11 @@ enum { MODAL_STAGE_GL = 0, MODAL_STAGE_LEGENDRE, MODAL_STAGE_BESSEL, MODAL_STAGE
        MODAL_STAGE_PREP, MODAL_STAGE_ADJ_PREP, MODAL_NSTAGES };
 modal_status modal_enable_timing(modal_ctx ctx, int on);
 modal_status modal_stage_times(modal_ctx ctx, double *ms, int n);
+/* How many timed intervals each stage of the last call recorded (stages
+ * that run in chunks record one per chunk: the Bessel/beta l chunks, and the
+ * r batches of modal_gamma_3d under _PREP); 0 when timing is off.  Does not
+ * wait for the stream.  n is the length of counts (>= MODAL_NSTAGES). */
+modal_status modal_stage_counts(modal_ctx ctx, int32_t *counts, int n);
 
 /* ------------------------------------------------------------------ */
 /* Stage entry points (step a)                                        */
@@ -263,8 +268,12 @@ modal_status modal_gamma_modal(modal_ctx ctx, const modal_grid *grid, const moda
  * symbol it equals modal_gamma's Gamma' up to rounding.  Same grid and
  * problem as modal_gamma (mu, wmu unused, nmu only validated as >= 1; both
  * kinds); FP64 throughout; host or device arrays as everywhere.
- * np * na <= 1280 (the workspace holds the full moment tensor,
- * 8 (np na)^3 bytes, plus about 4 GiB of operands).  gamma: [ta][tp]. */
+ * np * na = U <= 1280.  Workspace: the moment tensor over u1 and the pairs
+ * u2 <= u3, 4 U^2 (U + 1) bytes, beta and the Bessel chunks as in the
+ * forward, and the operands of one batch of nb radial points,
+ * 8 nb (2 L U + U^2 + U (U + 1) / 2 + U) bytes.  r is taken in balanced
+ * batches of at most the count whose operands fit in 8 GiB, or in a quarter
+ * of the workspace limit when one is set.  gamma: [ta][tp]. */
 modal_status modal_gamma_3d(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
                             int32_t threej, double *gamma);
 

@@ -4,9 +4,6 @@
 // the boundary: every entry point returns a modal_status.
 #include "internal.hpp"
 
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
-
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -24,7 +21,7 @@ enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
     W_S32, W_SH, W_SL, W_GAMMA,
     W_INVA, W_INVP, W_H, W_SHAT, W_BHAT, W_AHAT, W_DQ, W_DD, W_GRAM, W_INFO,
-    W_G3, W_A3, W_B3, W_C3, W_K3, W_T3, W_P3, W_V3,
+    W_G3, W_A3, W_B3, W_C3, W_K3, W_T3, W_P3, W_V3, W_FLAG,
     W_IN0, NSLOTS = W_IN0 + 16
 };
 
@@ -85,7 +82,6 @@ struct modal_ctx_s {
     bool timing = false;
     bool reuse_fwd = false;            // modal_set_forward_reuse
     FwdCache fwd;
-    rocblas_handle blas = nullptr;     // for the solve of the full Gamma (created on first use)
     // per stage: a pool of (start, end) event pairs; the first `used` belong
     // to the last call (chunked stages record one pair per chunk)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MODAL_NSTAGES];
@@ -259,6 +255,23 @@ void zero(modal_ctx c, double *p, int64_t n)
     hipck(c, hipGetLastError(), "zero fill");
 }
 
+// flag[0] = 1 if any of the n values is not finite (every writer stores the
+// same value, so the unordered stores need no atomics); flag is cleared by
+// the caller with the fill kernel first.
+__global__ void k_flag_nonfinite(const double *__restrict__ p, int64_t n, int *__restrict__ flag)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(p[i]);
+    if (bad) flag[0] = 1;
+}
+
+__global__ void k_zero_int(int *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // Zero the padding rows U..upad of every 32-wide z block of a z-blocked array.
 __global__ void k_zero_pad_rows(double *St, int64_t nzb, int64_t upad, int64_t U)
 {
@@ -325,7 +338,31 @@ Dims check_grid(modal_ctx c, const modal_grid *g, bool need_mu_rule)
     return d;
 }
 
-void check_problem(modal_ctx c, const modal_problem *p, Dims &d, bool need_delta, bool need_tri)
+// Every value of a caller array (host or device) must be finite: a NaN or an
+// infinity in Delta, q or qbar would otherwise run through every stage and
+// surface only as a non-finite Gamma.  Device arrays are scanned by a kernel
+// on the context's stream (one flag read back); host arrays on the host.
+void check_finite(modal_ctx c, const double *p, size_t n, const char *msg)
+{
+    if (!p || n == 0) return;
+    if (!is_device_ptr(c, p)) {
+        for (size_t i = 0; i < n; ++i) need(c, std::isfinite(p[i]), MODAL_ERR_NUMERIC, msg);
+        return;
+    }
+    int *flag = (int *)ws_get(c, W_FLAG, sizeof(int));
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c->stream, flag, 1);
+    hipck(c, hipGetLastError(), "zero fill");
+    const int64_t blocks = std::min<int64_t>(4096, ((int64_t)n + 255) / 256);
+    hipLaunchKernelGGL(k_flag_nonfinite, dim3((unsigned)blocks), dim3(256), 0, c->stream, p, (int64_t)n, flag);
+    hipck(c, hipGetLastError(), "finiteness scan");
+    int h = 0;
+    hipck(c, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "D2H");
+    hipck(c, hipStreamSynchronize(c->stream), "sync");
+    need(c, h == 0, MODAL_ERR_NUMERIC, msg);
+}
+
+void check_problem(modal_ctx c, const modal_problem *p, Dims &d, bool need_delta, bool need_tri,
+                   bool scan_values = true)
 {
     need(c, p != nullptr, MODAL_ERR_INVALID_ARG, "problem is NULL");
     need(c, p->np >= 1 && p->na >= 1, MODAL_ERR_SHAPE, "np and na must be >= 1");
@@ -338,6 +375,11 @@ void check_problem(modal_ctx c, const modal_problem *p, Dims &d, bool need_delta
     d.U = p->np * p->na;
     auto cl = host_copy(c, p->cl, (size_t)d.L);
     for (double v : cl) need(c, v > 0.0 && std::isfinite(v), MODAL_ERR_NUMERIC, "C_l must be finite and > 0");
+    if (scan_values) check_finite(c, p->ql, (size_t)d.na * d.L, "qbar_a(l) must be finite");
+    if (need_delta && scan_values) {
+        check_finite(c, p->delta, (size_t)d.L * d.nk, "Delta_l(k) must be finite");
+        check_finite(c, p->qk, (size_t)d.np * d.nk, "q_p(k) must be finite");
+    }
     if (need_tri) {
         need(c, p->kind == MODAL_GAMMA_ORDERED || p->kind == MODAL_GAMMA_SYMMETRIC, MODAL_ERR_INVALID_ARG,
              "kind must be MODAL_GAMMA_ORDERED or MODAL_GAMMA_SYMMETRIC");
@@ -596,24 +638,24 @@ void run_gram(modal_ctx c, const modal_grid *g, const modal_problem *p, const Di
     run_triple_gather(c, &pg, dg, prec, St, gram);
 }
 
-void blas_ok(modal_ctx c, rocblas_status st, const char *what)
-{
-    if (st != rocblas_status_success)
-        fail(c, MODAL_ERR_DEVICE, std::string(what) + ": " + rocblas_status_to_string(st));
-}
-
-void blas_bind(modal_ctx c)
-{
-    if (!c->blas) blas_ok(c, rocblas_create_handle(&c->blas), "rocblas_create_handle");
-    blas_ok(c, rocblas_set_stream(c->blas, c->stream), "rocblas_set_stream");
-}
-
 // Gamma' of Eq. (3D) with the exact (threej = MODAL_3J_EXACT) or Gosper
 // symbol: the moment tensor T contracted one l at a time (k_modal3d.hip),
-// then gathered.  The r axis is taken in batches so that the G and A
-// operands stay within about 2 GiB each.
+// then gathered; the three contractions per l1 run on the in-tree FP64
+// matrix-core GEMM (k_dgemm.hip).  The r axis is taken in balanced batches
+// of at most nrb points, nrb the largest count whose batch operands fit the
+// batch budget (8 GiB, or a quarter of the workspace limit when one is set).
 constexpr int kRowChunk3d = 128;
 constexpr int kU2Block3d = 128;
+constexpr size_t kBatchBudget3d = (size_t)8 << 30;
+
+// bytes of the batch operands (G, A, B_r, packed B_r, C) per radial point
+size_t batch_bytes_per_r3d(int L, int U)
+{
+    const size_t NT = (size_t)U * (U + 1) / 2;
+    return sizeof(double) * (2 * (size_t)L * U + (size_t)U * U + NT + (size_t)U);
+}
+
+void dg(modal_ctx c, hipError_t e, const char *what) { hipck(c, e, what); }
 
 void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, const Dims &d, int threej,
                   double *gamma)
@@ -639,7 +681,11 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
     const int nO = lO0 <= g->lmax ? (g->lmax - lO0) / 2 + 1 : 0;
     const int l0c[2] = {lE0, lO0}, nc[2] = {nE, nO}, offc[2] = {0, nE};
     const size_t per_r = (size_t)L * U * sizeof(double);
-    const int nrb = (int)std::max<size_t>(1, std::min<size_t>((size_t)d.nr, ((size_t)2 << 30) / per_r));
+    size_t budget = kBatchBudget3d;
+    if (c->limit) budget = std::min(budget, c->limit / 4);
+    const size_t nrb_max = std::max<size_t>(1, std::min<size_t>((size_t)d.nr, budget / batch_bytes_per_r3d(L, U)));
+    const int nbatch = (int)((d.nr + nrb_max - 1) / nrb_max);
+    const int nrb = (d.nr + nbatch - 1) / nbatch;
     double *Gb = (double *)ws_get(c, W_G3, per_r * nrb);
     double *Ab = (double *)ws_get(c, W_A3, per_r * nrb);
     double *Bb = (double *)ws_get(c, W_B3, sizeof(double) * (size_t)U * U * nrb);
@@ -657,18 +703,23 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
     // start values of the symbol bands, (l1 l2 |l1 - l2|; 000)^2 by max and min
     double *V = (double *)ws_get(c, W_V3, sizeof(double) * ((size_t)g->lmax + 1) * (g->lmax + 2) / 2);
     hipck(c, launch_start3(g->lmax, V, c->stream), "Eq. (3D) band starts");
-    blas_bind(c);
-    const double one = 1.0, nil = 0.0;
     for (int r0 = 0; r0 < d.nr; r0 += nrb) {
         const int nb = std::min(nrb, d.nr - r0);
-        hipck(c, launch_build_g3(L, nE, lE0, lO0, g->lmin, d.nr, d.np, d.na, r0, nb, wl, ql, beta, Gb, c->stream),
-              "Eq. (3D) operand");
+        {
+            StageTimer tm(c, MODAL_STAGE_PREP);     // one interval per r batch
+            hipck(c, launch_build_g3(L, nE, lE0, lO0, g->lmin, d.nr, d.np, d.na, r0, nb, wl, ql, beta, Gb,
+                                     c->stream),
+                  "Eq. (3D) operand");
+        }
+        StageTimer tm(c, MODAL_STAGE_TRIPLE);
         for (int l1 = g->lmin; l1 <= g->lmax; ++l1) {
             const int p1 = l1 & 1;
             hipck(c, launch_build_k3(l1, l0c, nc, threej == MODAL_3J_GOSPER, V, Kb, Kb + kblk, c->stream),
                   "Eq. (3D) symbols");
+            // stage 1: A_r(l2, u) = Sum_l3 K(l2, l3) G_r(l3, u), per parity
+            // class of l2 (class 0 = even l, 1 = odd l; l3 has the parity of
+            // l1 + l2)
             for (int par2 = 0; par2 < 2; ++par2) {
-                // class 0 = even l, 1 = odd l; l3 has the parity of l1 + l2
                 const int par3 = (p1 + par2) & 1;
                 const int n2 = nc[par2], n3 = nc[par3];
                 if (n2 == 0) continue;
@@ -692,44 +743,42 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
                               "Eq. (3D) empty rows");
                         continue;
                     }
-                    blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, i2b - i2a, nb * U,
-                                             c1 - c0 + 1, &one, Kp + (size_t)c0 * n2 + i2a, n2,
-                                             Gb + offc[par3] + c0, L, &nil, Ab + offc[par2] + i2a, L),
-                            "Eq. (3D) stage 1");
+                    dg(c, launch_dgemm(false, false, i2b - i2a, nb * U, c1 - c0 + 1, 1.0, Kp + (size_t)c0 * n2 + i2a,
+                                       n2, 0, Gb + offc[par3] + c0, L, 0, 0.0, Ab + offc[par2] + i2a, L, 0, 1,
+                                       c->stream),
+                       "Eq. (3D) stage 1");
                 }
             }
-            // B_r = G_r^T K G_r is symmetric (K is symmetric in l2, l3): of
-            // its 2 x 2 blocks only the three on or above the diagonal, then
-            // the upper triangle packed (u2-major pairs)
+            // stage 2: B_r = G_r^T A_r is symmetric (K is symmetric in l2,
+            // l3): of its 2 x 2 blocks only the three on or above the
+            // diagonal, split on a multiple of the GEMM tile edge, then the
+            // upper triangle packed (u2-major pairs)
             {
-                // the split on a multiple of 64 (the GEMM's tile edge), so
-                // that fewer tiles straddle a block edge
-                const int h = std::min(U, pad_to((U + 1) / 2, 64));
+                const int h = std::min(U, pad_to((U + 1) / 2, 128));
                 const int off[3][2] = {{0, 0}, {0, h}, {h, h}};
                 for (int b = 0; b < 3; ++b) {
                     const int u0 = off[b][0], v0 = off[b][1];
                     const int mu = (u0 == 0 ? h : U - h), nv = (v0 == 0 ? h : U - h);
                     if (mu <= 0 || nv <= 0) continue;
-                    blas_ok(c, rocblas_dgemm_strided_batched(c->blas, rocblas_operation_transpose, rocblas_operation_none,
-                                                             mu, nv, L, &one, Gb + (size_t)u0 * L, L,
-                                                             (rocblas_stride)U * L, Ab + (size_t)v0 * L, L,
-                                                             (rocblas_stride)U * L, &nil, Bb + u0 + (size_t)v0 * U, U,
-                                                             (rocblas_stride)U * U, nb),
-                            "Eq. (3D) stage 2");
+                    dg(c, launch_dgemm(true, false, mu, nv, L, 1.0, Gb + (size_t)u0 * L, L, (int64_t)U * L,
+                                       Ab + (size_t)v0 * L, L, (int64_t)U * L, 0.0, Bb + u0 + (size_t)v0 * U, U,
+                                       (int64_t)U * U, nb, c->stream),
+                       "Eq. (3D) stage 2");
                 }
             }
             hipck(c, launch_pack3(U, nb, Bb, Pb, c->stream), "Eq. (3D) pack");
             const int lp1 = p1 == 0 ? (l1 - lE0) / 2 : nE + (l1 - lO0) / 2;
             hipck(c, launch_c3(L, lp1, U, r0, nb, G.r, G.wr, Gb, Cb, c->stream), "Eq. (3D) radial weights");
-            // T(u1, (u2, u3)) for u1 below the end of the u2 block: u1 <= u2 <= u3
-            // is all the gather reads
+            // stage 3: T(u1, (u2, u3)) += Sum_r C_r(u1) B_r(u2, u3), for u1
+            // below the end of each u2 block: u1 <= u2 <= u3 is all the
+            // gather reads
             for (int b0 = 0; b0 < U; b0 += kU2Block3d) {
                 const int b1 = std::min(U, b0 + kU2Block3d);
                 const int64_t t0 = (int64_t)b0 * U - (int64_t)b0 * (b0 - 1) / 2;
                 const int64_t t1 = (int64_t)b1 * U - (int64_t)b1 * (b1 - 1) / 2;
-                blas_ok(c, rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_transpose, b1,
-                                         (int)(t1 - t0), nb, &one, Cb, U, Pb + t0, NT, &one, T + (size_t)t0 * U, U),
-                        "Eq. (3D) stage 3");
+                dg(c, launch_dgemm(false, true, b1, (int)(t1 - t0), nb, 1.0, Cb, U, 0, Pb + t0, NT, 0, 1.0,
+                                   T + (size_t)t0 * U, U, 0, 1, c->stream),
+                   "Eq. (3D) stage 3");
             }
         }
     }
@@ -741,25 +790,59 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
 // x (row-major [n][m], on the device) := gram^-1 x, gram SPD [n][n] (on the
 // device, overwritten by its Cholesky factor).  Read column major, x is its
 // transpose X' (m x n), and X' gram^-1 = X' L^-T L^-1 for gram = L L^T: two
-// triangular solves from the right.
+// triangular solves from the right.  All in-tree: a right-looking blocked
+// Cholesky (64-wide diagonal blocks factored in LDS, the panel below solved
+// row by row, the trailing block updated on the FP64 GEMM), then each
+// triangular solve blocked the same way (the columns of one block solved
+// per row of X' against the diagonal block, the rest by GEMM updates).
 void solve_gram(modal_ctx c, int n, int m, double *gram, double *x)
 {
     if (n == 0 || m == 0) return;
-    if (!c->blas) blas_ok(c, rocblas_create_handle(&c->blas), "rocblas_create_handle");
-    blas_ok(c, rocblas_set_stream(c->blas, c->stream), "rocblas_set_stream");
-    rocblas_int *info = (rocblas_int *)ws_get(c, W_INFO, sizeof(rocblas_int));
-    blas_ok(c, rocsolver_dpotrf(c->blas, rocblas_fill_lower, n, gram, n, info), "Cholesky factorisation");
-    rocblas_int hinfo = 0;
+    const int nb = chol_block();
+    int *info = (int *)ws_get(c, W_INFO, sizeof(int));
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c->stream, info, 1);
+    hipck(c, hipGetLastError(), "zero fill");
+    double *A = gram;
+    for (int j0 = 0; j0 < n; j0 += nb) {
+        const int jb = std::min(nb, n - j0), j1 = j0 + jb, rest = n - j1;
+        double *D = A + (size_t)j0 * n + j0;
+        hipck(c, launch_potrf_block(jb, D, n, info, c->stream), "Cholesky diagonal block");
+        if (rest == 0) break;
+        // panel: A21 := A21 L11^-T, one row of A21 per vector
+        double *P = A + (size_t)j0 * n + j1;
+        hipck(c, launch_trsm_rows(rest, jb, D, n, P, 1, n, 0, c->stream), "Cholesky panel");
+        // trailing block: A22 -= A21 A21^T
+        hipck(c, launch_dgemm(false, true, rest, rest, jb, -1.0, P, n, 0, P, n, 0, 1.0, A + (size_t)j1 * n + j1, n,
+                              0, 1, c->stream),
+              "Cholesky update");
+    }
+    int hinfo = 0;
     hipck(c, hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream), "D2H");
     hipck(c, hipStreamSynchronize(c->stream), "synchronise");
     need(c, hinfo == 0, MODAL_ERR_NUMERIC, "the Gram matrix <Q, Q> is not positive definite");
-    const double one = 1.0;
-    blas_ok(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                             rocblas_diagonal_non_unit, m, n, &one, gram, n, x, m),
-            "triangular solve");
-    blas_ok(c, rocblas_dtrsm(c->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_none,
-                             rocblas_diagonal_non_unit, m, n, &one, gram, n, x, m),
-            "triangular solve");
+    // X' := X' L^-T: block columns forward, X'_J -= X'_{<J} L_{J,<J}^T, then
+    // the diagonal block
+    for (int j0 = 0; j0 < n; j0 += nb) {
+        const int jb = std::min(nb, n - j0);
+        if (j0 > 0)
+            hipck(c, launch_dgemm(false, true, m, jb, j0, -1.0, x, m, 0, A + j0, n, 0, 1.0, x + (size_t)j0 * m, m, 0,
+                                  1, c->stream),
+                  "triangular solve update");
+        hipck(c, launch_trsm_rows(m, jb, A + (size_t)j0 * n + j0, n, x + (size_t)j0 * m, 1, m, 0, c->stream),
+              "triangular solve");
+    }
+    // X' := X' L^-1: block columns backward, X'_J -= X'_{>J} L_{>J,J}, then
+    // the diagonal block
+    const int last = (n - 1) / nb * nb;
+    for (int j0 = last; j0 >= 0; j0 -= nb) {
+        const int jb = std::min(nb, n - j0), j1 = j0 + jb;
+        if (j1 < n)
+            hipck(c, launch_dgemm(false, false, m, jb, n - j1, -1.0, x + (size_t)j1 * m, m, 0, A + (size_t)j0 * n + j1,
+                                  n, 0, 1.0, x + (size_t)j0 * m, m, 0, 1, c->stream),
+                  "triangular solve update");
+        hipck(c, launch_trsm_rows(m, jb, A + (size_t)j0 * n + j0, n, x + (size_t)j0 * m, 1, m, 1, c->stream),
+              "triangular solve");
+    }
 }
 
 }  // namespace
@@ -809,7 +892,6 @@ modal_status modal_destroy(modal_ctx c)
     for (auto &b : c->ws) (void)hipFree(b.p);
     free_triple_plan(c->plan64);
     free_bt_plan(c->planbt);
-    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     for (auto &pool : c->ev)
         for (auto &pr : pool) {
             (void)hipEventDestroy(pr.first);
@@ -822,7 +904,23 @@ modal_status modal_destroy(modal_ctx c)
 modal_status modal_set_stream(modal_ctx c, void *hip_stream)
 {
     if (!c) return MODAL_ERR_INVALID_ARG;
-    c->stream = (hipStream_t)hip_stream;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    if (s == c->stream) return MODAL_OK;
+    // work already queued on the old stream (which may still read or write
+    // the workspace) is ordered before anything the new stream runs next
+    c->next_in = 0;
+    try {
+        hipck(c, hipSetDevice(c->device), "hipSetDevice");
+        hipEvent_t ev = nullptr;
+        hipck(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event create");
+        hipError_t e = hipEventRecord(ev, c->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+        (void)hipEventDestroy(ev);
+        hipck(c, e, "ordering the new stream after the old one");
+    } catch (const Fail &x) {
+        return x.st;
+    }
+    c->stream = s;
     return MODAL_OK;
 }
 
@@ -892,6 +990,13 @@ modal_status modal_stage_times(modal_ctx c, double *ms, int n)
     return MODAL_OK;
 }
 
+modal_status modal_stage_counts(modal_ctx c, int32_t *counts, int n)
+{
+    if (!c || !counts || n < MODAL_NSTAGES) return MODAL_ERR_INVALID_ARG;
+    for (int s = 0; s < MODAL_NSTAGES; ++s) counts[s] = c->timing ? c->used[s] : 0;
+    return MODAL_OK;
+}
+
 modal_status modal_workspace_bytes(modal_ctx c, const modal_grid *g, const modal_problem *p,
                                    modal_precision prec, size_t *bytes)
 {
@@ -900,7 +1005,7 @@ modal_status modal_workspace_bytes(modal_ctx c, const modal_grid *g, const modal
         need(c, bytes != nullptr, MODAL_ERR_INVALID_ARG, "bytes is NULL");
         check_prec(c, prec);
         Dims d = check_grid(c, g, false);
-        check_problem(c, p, d, true, false);
+        check_problem(c, p, d, true, false, false);
         const size_t Upad = (size_t)pad_to(d.U, kRowPad);
         const size_t z = (size_t)d.nr * d.ldmu;
         const size_t nitems = (size_t)d.nk * d.nr;

@@ -193,6 +193,22 @@ hipError_t launch_zero_rows3(int64_t ld, int row0, int nrows, int64_t ncols, dou
 hipError_t launch_gather3(int kind, int ta, int tp, const int *tri_a, const int *tri_p, int np, int U,
                           const double *T, double *gamma, hipStream_t s);
 
+// Column-major FP64 matrix-core GEMM (k_dgemm.hip), strided batches:
+// C_b = alpha op(A_b) op(B_b) + beta C_b with op(A)(m, k) = ta ? A[k + m lda]
+// : A[m + k lda], op(B)(k, n) = tb ? B[n + k ldb] : B[k + n ldb].
+hipError_t launch_dgemm(bool ta, bool tb, int m, int n, int k, double alpha, const double *A, int64_t lda,
+                        int64_t sA, const double *B, int64_t ldb, int64_t sB, double beta, double *C,
+                        int64_t ldc, int64_t sC, int batch, hipStream_t s);
+
+// Blocked Cholesky pieces (k_chol.hip): factor one diagonal block (at most
+// chol_block() wide; *info = 1 if it is not positive definite), and solve
+// rows vectors (element j of vector i at X[i xr + j xc]) against the lower
+// block L: x L^T = x (backward = 0) or x L = x (backward = 1).
+int chol_block();
+hipError_t launch_potrf_block(int jb, double *A, int64_t lda, int *info, hipStream_t s);
+hipError_t launch_trsm_rows(int rows, int jb, const double *L, int64_t ldl, double *X, int64_t xr, int64_t xc,
+                            int backward, hipStream_t s);
+
 hipError_t launch_gather(int kind, int ta, int tp, const int *tri_a, const int *tri_p,
                          int np, const TriplePlan &plan, const double *T, double *gamma,
                          hipStream_t s);

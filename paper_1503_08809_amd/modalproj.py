@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
             "modal_enable_timing": [vp, ctypes.c_int],
             "modal_set_forward_reuse": [vp, ctypes.c_int],
             "modal_stage_times": [vp, _dp, ctypes.c_int],
+            "modal_stage_counts": [vp, ctypes.POINTER(i32), ctypes.c_int],
             "modal_gauss_legendre": [vp, i32, vp, vp],
             "modal_legendre_table": [vp, i32, i32, vp, vp],
             "modal_sph_bessel_table": [vp, i32, i64, vp, vp],
@@ -105,7 +106,7 @@ def exported_symbols():
     """Names of the C entry points the binding declares."""
     return ["modal_create", "modal_destroy", "modal_set_stream", "modal_status_str",
             "modal_last_error", "modal_set_workspace_limit", "modal_workspace_bytes",
-            "modal_enable_timing", "modal_stage_times", "modal_set_forward_reuse",
+            "modal_enable_timing", "modal_stage_times", "modal_stage_counts", "modal_set_forward_reuse",
             "modal_gauss_legendre",
             "modal_legendre_table", "modal_sph_bessel_table", "modal_beta", "modal_S",
             "modal_gamma_from_S", "modal_gamma", "modal_gram", "modal_gamma_modal",
@@ -123,8 +124,10 @@ def _ptr(x) -> Optional[int]:
 
 
 class Context:
-    """A library context on one device; work goes on torch's current stream
-    of that device unless a stream is given."""
+    """A library context on one device.  Without a stream, every call runs on
+    torch's current stream of that device at the time of the call (the
+    library is switched to it, ordered after its earlier work, whenever it
+    changes); with a stream, always on that one."""
 
     def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
         L = lib()
@@ -133,12 +136,26 @@ class Context:
         self.device = device
         self.forward_reuse = False
         self.torch_device = torch.device("cuda", device)
+        self._follow = stream is None
         if stream is None:
             stream = torch.cuda.current_stream(self.torch_device)
         self.stream = stream
         h = ctypes.c_void_p()
         self._check(L.modal_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)), None)
-        self.handle = h
+        self._h = h
+
+    @property
+    def handle(self):
+        """The library handle; every call reaches it through here, so a
+        context that follows torch's current stream is switched to it first
+        (modal_set_stream orders the new stream after the old one)."""
+        h = self._h
+        if h is not None and self._follow:
+            s = torch.cuda.current_stream(self.torch_device)
+            if s.cuda_stream != self.stream.cuda_stream:
+                self._check(lib().modal_set_stream(h, ctypes.c_void_p(s.cuda_stream)), h)
+                self.stream = s
+        return h
 
     def _check(self, st: int, handle):
         if st != 0:
@@ -148,12 +165,12 @@ class Context:
             raise ModalError(st, msg or L.modal_status_str(st).decode())
 
     def check(self, st: int):
-        self._check(st, self.handle)
+        self._check(st, self._h)
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().modal_destroy(self.handle)
-            self.handle = None
+        if getattr(self, "_h", None):
+            lib().modal_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:
@@ -178,6 +195,12 @@ class Context:
         ms = (ctypes.c_double * len(STAGES))()
         self.check(lib().modal_stage_times(self.handle, ms, len(STAGES)))
         return {name: float(ms[i]) for i, name in enumerate(STAGES)}
+
+    def stage_counts(self) -> dict:
+        """Timed intervals per stage of the last call (one per chunk or batch)."""
+        n = (ctypes.c_int32 * len(STAGES))()
+        self.check(lib().modal_stage_counts(self._h, n, len(STAGES)))
+        return {name: int(n[i]) for i, name in enumerate(STAGES)}
 
     def empty(self, *shape, dtype=torch.float64):
         return torch.empty(*shape, dtype=dtype, device=self.torch_device)

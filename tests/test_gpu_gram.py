@@ -72,6 +72,27 @@ def test_gamma_modal_vs_oracle(mp, ctx, oracle, kind, n1, lmax, nr, nk):
     assert e64 <= 1e-8 and bm <= 1e-4
 
 
+@pytest.mark.parametrize("n1,lmax", [(5, 40), (6, 60)])
+def test_gamma_modal_blocked_solve(mp, ctx, oracle, n1, lmax):
+    """Ordered lists of 125 and 216 modes: the blocked Cholesky runs over
+    two and four 64-wide diagonal blocks (the last ragged) with GEMM updates
+    between them.  <Q, Q> is positive definite here (condition number 5.7e6
+    and 8.6e8).  FP64: backward error with the oracle's <Q, Q> and Gamma'
+    <= 1e-12, forward error against numpy's solve <= 1e-13 cond(<Q, Q>)."""
+    inp = synth.make_inputs(synth.small_config(lmax=lmax, nk=40, nr=3, n1=n1, kind="ordered", seed_index=94))
+    pr = mp.projection_from_inputs(ctx, inp)
+    gram, gp = oracle.gram_full(inp), oracle.gamma_full(inp)
+    ref = np.linalg.solve(gram, gp)
+    cond = float(np.linalg.cond(gram))
+    x64 = _np(pr.gamma_modal("fp64"))
+    b64 = float(np.abs(gram @ x64 - gp).max() / np.abs(gp).max())
+    e64 = normwise(x64, ref)
+    print(f"full Gamma ordered n1={n1} ({gram.shape[0]} modes, cond {cond:.1e}): backward {b64:.2e}, "
+          f"forward {e64:.2e}")
+    assert gram.shape[0] > 64
+    assert b64 <= 1e-12 and e64 <= 1e-13 * cond
+
+
 def test_gram_lmax2500_sampled(mp, ctx, oracle):
     """lmax = 2500, 4960 x 4960: sampled <Q, Q> entries (the lowest modes
     among them) against the oracle, FP64 and mixed, and the symmetry of the

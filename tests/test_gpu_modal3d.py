@@ -4,15 +4,17 @@ at lmax = 1000, against the separable path and stored oracle entries.
 
 Bars: FP64 normwise 1e-12 against the oracle at small sizes (the same sums
 in another order; the exact symbol comes from a recurrence within a few
-ulp); 1e-9 normwise against the separable GPU path and 1e-9 elementwise on
-the large stored entries at lmax = 1000 (the separable form loses more to
-the cancellation of its mu sums than this path does).
+ulp); 1e-9 normwise against the separable GPU path at lmax = 1000, and
+every stored oracle entry there within 1e-9 of its magnitude scale (the
+separable form loses more to the cancellation of its mu sums than this path
+does).
 """
 import time
 
 import numpy as np
 import pytest
 
+import stored_rows
 from paper_1503_08809_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -88,6 +90,51 @@ def test_3d_single_l(mp, ctx, oracle, l):
         assert np.abs(ref).max() > 0 and normwise(g, ref) <= 1e-13
 
 
+def _batch_bytes_per_r(L, U):
+    """Bytes of Eq. (3D)'s batch operands per radial point (the header's
+    formula: 8 (2 L U + U^2 + U (U + 1) / 2 + U))."""
+    return 8 * (2 * L * U + U * U + U * (U + 1) // 2 + U)
+
+
+@pytest.mark.parametrize("threej", ["exact", "gosper"])
+def test_3d_r_batches(mp, ctx, oracle, threej):
+    """Nr = 7 taken in three r batches (3, 3 and a ragged 1): a workspace
+    limit of 15 batch points gives at most 3 points per batch (a quarter of
+    the limit).  The batch count is read back from the stage counts; the
+    result against the oracle at 1e-12 and against the one-batch result."""
+    cfg = synth.small_config(lmax=30, nk=20, nr=7, n1=4, kind="symmetric", seed_index=96)
+    inp = synth.make_inputs(cfg)
+    U = inp.ql.shape[0] * inp.qk.shape[0]
+    c2 = mp.Context(0)
+    try:
+        c2.set_workspace_limit(15 * _batch_bytes_per_r(cfg.L, U))
+        c2.enable_timing(True)
+        g = _np(mp.projection_from_inputs(c2, inp).gamma_3d(threej))
+        n = c2.stage_counts()["prep"]
+    finally:
+        c2.close()
+    ref = oracle.gamma_3d(inp, threej)
+    one = _np(mp.projection_from_inputs(ctx, inp).gamma_3d(threej))
+    err, err1 = normwise(g, ref), normwise(g, one)
+    print(f"Eq. (3D) in {n} r batches, {threej}: vs oracle {err:.2e}, vs one batch {err1:.2e}")
+    assert n == 3
+    assert err <= 1e-12 and err1 <= 1e-13
+
+
+def test_3d_workspace_limit_too_small(mp, ctx):
+    """A limit below what one radial point needs is refused as OOM."""
+    cfg = synth.small_config(lmax=30, nk=20, nr=7, n1=4, kind="symmetric", seed_index=96)
+    inp = synth.make_inputs(cfg)
+    c2 = mp.Context(0)
+    try:
+        c2.set_workspace_limit(4 * 1024)
+        with pytest.raises(mp.ModalError) as e:
+            mp.projection_from_inputs(c2, inp).gamma_3d("exact")
+        assert e.value.status == 3
+    finally:
+        c2.close()
+
+
 @pytest.mark.parametrize("kind,n1,lmax,nr", [("symmetric", 4, 300, 6), ("ordered", 3, 517, 5)])
 def test_3d_vs_separable(mp, ctx, kind, n1, lmax, nr):
     """Several 128-row chunks of the l3 band and an odd lmax: Eq. (3D) (exact
@@ -103,7 +150,6 @@ def test_3d_lmax1000(mp, ctx):
     """lmax = 1000, Nr = 300, 1540 x 1540 symmetric: Eq. (3D) with the exact
     symbol against Eq. (2D) on the GPU and against stored oracle entries; the
     Gosper symbol's distance from it."""
-    import os
     import torch
     cfg = synth.workload("lmax1000_symmetric_n20")
     inp = synth.make_inputs(cfg)
@@ -113,19 +159,16 @@ def test_3d_lmax1000(mp, ctx):
     g3 = _np(pr.gamma_3d("exact"))
     t3 = time.perf_counter() - t
     g2 = _np(pr.gamma("fp64"))
-    path = os.path.join(os.path.dirname(__file__), "golden", f"oracle_gamma_{cfg.name}.txt")
-    a = np.loadtxt(path, comments="#", ndmin=2)
-    rows, cols, ref = a[:, 0].astype(np.int64), a[:, 1].astype(np.int64), a[:, 2]
+    rows, cols, ref, sc = stored_rows.load(cfg.name)
     scale = np.abs(g3).max()
     e2 = normwise(g3, g2)
     eo = float(np.abs(g3[rows, cols] - ref).max() / scale)
-    big = np.abs(ref) >= 1e-3 * scale
-    rel = float((np.abs(g3[rows, cols] - ref)[big] / np.abs(ref[big])).max())
+    ew = stored_rows.worst(g3[rows, cols], ref, sc)
     gg = _np(pr.gamma_3d("gosper"))
     eg = normwise(gg, g3)
-    print(f"Eq. (3D) lmax=1000: {t3:.2f} s; vs Eq. (2D) {e2:.2e}; vs oracle {eo:.2e} "
-          f"({int(big.sum())} large entries, elementwise {rel:.2e}); Gosper symbol vs exact {eg:.2e}")
-    assert e2 <= 1e-9 and eo <= 1e-9 and big.sum() >= 1 and rel <= 1e-9
+    print(f"Eq. (3D) lmax=1000: {t3:.2f} s; vs Eq. (2D) {e2:.2e}; vs oracle rows {eo:.2e} normwise, "
+          f"{ew:.2e} of the entry scale ({rows.size} entries); Gosper symbol vs exact {eg:.2e}")
+    assert e2 <= 1e-9 and eo <= 1e-9 and ew <= stored_rows.FP64_TOL
     # the Gosper form moves Gamma' by its weighted error (2.3 % at worst per
     # symbol, far less where every L_i is large), not by a dropped factor
     assert 1e-6 < eg < 1e-2
