@@ -271,7 +271,7 @@ modal_status modal_gamma_modal(modal_ctx ctx, const modal_grid *grid, const moda
  * np * na = U <= 1280.  Workspace: the moment tensor over u1 and the pairs
  * u2 <= u3, 4 U^2 (U + 1) bytes, beta and the Bessel chunks as in the
  * forward, and the operands of one batch of nb radial points,
- * 8 nb (2 L U + U^2 + U (U + 1) / 2 + U) bytes.  r is taken in balanced
+ * 8 nb (2 L U + U (U + 1) / 2 + U) bytes.  r is taken in balanced
  * batches of at most the count whose operands fit in 8 GiB, or in a quarter
  * of the workspace limit when one is set.  gamma: [ta][tp]. */
 modal_status modal_gamma_3d(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,

@@ -21,7 +21,7 @@ enum Slot {
     W_MU, W_WMU, W_P, W_WL, W_WZ, W_BSTATE, W_JCHUNK, W_BETA, W_ST, W_T,
     W_S32, W_SH, W_SL, W_GAMMA,
     W_INVA, W_INVP, W_H, W_SHAT, W_BHAT, W_AHAT, W_DQ, W_DD, W_GRAM, W_INFO,
-    W_G3, W_A3, W_B3, W_C3, W_K3, W_T3, W_P3, W_V3, W_FLAG,
+    W_G3, W_A3, W_C3, W_K3, W_T3, W_P3, W_V3, W_FLAG,
     W_IN0, NSLOTS = W_IN0 + 16
 };
 
@@ -641,18 +641,20 @@ void run_gram(modal_ctx c, const modal_grid *g, const modal_problem *p, const Di
 // Gamma' of Eq. (3D) with the exact (threej = MODAL_3J_EXACT) or Gosper
 // symbol: the moment tensor T contracted one l at a time (k_modal3d.hip),
 // then gathered; the three contractions per l1 run on the in-tree FP64
-// matrix-core GEMM (k_dgemm.hip).  The r axis is taken in balanced batches
+// matrix-core GEMM (k_dgemm.hip) with 64-wide output tiles (measured at
+// lmax = 1000: 3.57 s per call against 3.80 s with 128-wide tiles in
+// stages 1 and 3, whose row counts are 128 and up to U).  The r axis is taken in balanced batches
 // of at most nrb points, nrb the largest count whose batch operands fit the
 // batch budget (8 GiB, or a quarter of the workspace limit when one is set).
 constexpr int kRowChunk3d = 128;
 constexpr int kU2Block3d = 128;
 constexpr size_t kBatchBudget3d = (size_t)8 << 30;
 
-// bytes of the batch operands (G, A, B_r, packed B_r, C) per radial point
+// bytes of the batch operands (G, A, packed B_r, C) per radial point
 size_t batch_bytes_per_r3d(int L, int U)
 {
     const size_t NT = (size_t)U * (U + 1) / 2;
-    return sizeof(double) * (2 * (size_t)L * U + (size_t)U * U + NT + (size_t)U);
+    return sizeof(double) * (2 * (size_t)L * U + NT + (size_t)U);
 }
 
 void dg(modal_ctx c, hipError_t e, const char *what) { hipck(c, e, what); }
@@ -688,7 +690,6 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
     const int nrb = (d.nr + nbatch - 1) / nbatch;
     double *Gb = (double *)ws_get(c, W_G3, per_r * nrb);
     double *Ab = (double *)ws_get(c, W_A3, per_r * nrb);
-    double *Bb = (double *)ws_get(c, W_B3, sizeof(double) * (size_t)U * U * nrb);
     double *Cb = (double *)ws_get(c, W_C3, sizeof(double) * (size_t)U * nrb);
     // the symbol blocks of both parity classes of l2 for one l1
     const size_t kblk = std::max<size_t>(1, (size_t)std::max(nE, nO) * std::max(nE, nO));
@@ -745,28 +746,16 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
                     }
                     dg(c, launch_dgemm(false, false, i2b - i2a, nb * U, c1 - c0 + 1, 1.0, Kp + (size_t)c0 * n2 + i2a,
                                        n2, 0, Gb + offc[par3] + c0, L, 0, 0.0, Ab + offc[par2] + i2a, L, 0, 1,
-                                       c->stream),
+                                       c->stream, 64),
                        "Eq. (3D) stage 1");
                 }
             }
             // stage 2: B_r = G_r^T A_r is symmetric (K is symmetric in l2,
-            // l3): of its 2 x 2 blocks only the three on or above the
-            // diagonal, split on a multiple of the GEMM tile edge, then the
-            // upper triangle packed (u2-major pairs)
-            {
-                const int h = std::min(U, pad_to((U + 1) / 2, 128));
-                const int off[3][2] = {{0, 0}, {0, h}, {h, h}};
-                for (int b = 0; b < 3; ++b) {
-                    const int u0 = off[b][0], v0 = off[b][1];
-                    const int mu = (u0 == 0 ? h : U - h), nv = (v0 == 0 ? h : U - h);
-                    if (mu <= 0 || nv <= 0) continue;
-                    dg(c, launch_dgemm(true, false, mu, nv, L, 1.0, Gb + (size_t)u0 * L, L, (int64_t)U * L,
-                                       Ab + (size_t)v0 * L, L, (int64_t)U * L, 0.0, Bb + u0 + (size_t)v0 * U, U,
-                                       (int64_t)U * U, nb, c->stream),
-                       "Eq. (3D) stage 2");
-                }
-            }
-            hipck(c, launch_pack3(U, nb, Bb, Pb, c->stream), "Eq. (3D) pack");
+            // l3): only its upper triangle u <= v, formed as the lower one of
+            // B_r^T = A_r^T G_r and written straight into the u2-major pairs
+            dg(c, launch_dgemm_packed_lower(true, false, U, L, Ab, L, (int64_t)U * L, Gb, L, (int64_t)U * L, Pb, NT,
+                                            nb, c->stream),
+               "Eq. (3D) stage 2");
             const int lp1 = p1 == 0 ? (l1 - lE0) / 2 : nE + (l1 - lO0) / 2;
             hipck(c, launch_c3(L, lp1, U, r0, nb, G.r, G.wr, Gb, Cb, c->stream), "Eq. (3D) radial weights");
             // stage 3: T(u1, (u2, u3)) += Sum_r C_r(u1) B_r(u2, u3), for u1
@@ -777,7 +766,7 @@ void run_gamma_3d(modal_ctx c, const modal_grid *g, const modal_problem *p, cons
                 const int64_t t0 = (int64_t)b0 * U - (int64_t)b0 * (b0 - 1) / 2;
                 const int64_t t1 = (int64_t)b1 * U - (int64_t)b1 * (b1 - 1) / 2;
                 dg(c, launch_dgemm(false, true, b1, (int)(t1 - t0), nb, 1.0, Cb, U, 0, Pb + t0, NT, 0, 1.0,
-                                   T + (size_t)t0 * U, U, 0, 1, c->stream),
+                                   T + (size_t)t0 * U, U, 0, 1, c->stream, 64),
                    "Eq. (3D) stage 3");
             }
         }

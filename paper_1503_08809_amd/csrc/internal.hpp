@@ -179,8 +179,7 @@ hipError_t launch_dq_ddelta(int nl, int l0, int lmin, int np, int nk, const doub
 // Eq. (3D) (k_modal3d.hip): operand G[(rb U + u) L + l'] (l' parity-sorted,
 // even l first) for r in [r0, r0 + nrb); the band of 2 (3j)^2 for one l1 and
 // one pair of parity classes, K[i3 n2 + i2]; the r weights times the row l1'
-// of G, C[rb U + u]; the packing of the upper triangles of B_r (u2-major
-// pairs); and the gather of Gamma' from T(u1 <= u2 <= u3).
+// of G, C[rb U + u]; and the gather of Gamma' from T(u1 <= u2 <= u3).
 hipError_t launch_build_g3(int L, int nE, int lE0, int lO0, int lmin, int nr, int np, int na, int r0, int nrb,
                            const double *wl, const double *ql, const double *beta, double *G, hipStream_t s);
 hipError_t launch_start3(int lmax, double *V, hipStream_t s);
@@ -188,17 +187,23 @@ hipError_t launch_build_k3(int l1, const int l0[2], const int n[2], int gosper, 
                            double *K1, hipStream_t s);
 hipError_t launch_c3(int L, int lp1, int U, int r0, int nrb, const double *r, const double *wr, const double *G,
                      double *C, hipStream_t s);
-hipError_t launch_pack3(int U, int nrb, const double *B, double *P, hipStream_t s);
 hipError_t launch_zero_rows3(int64_t ld, int row0, int nrows, int64_t ncols, double *A, hipStream_t s);
 hipError_t launch_gather3(int kind, int ta, int tp, const int *tri_a, const int *tri_p, int np, int U,
                           const double *T, double *gamma, hipStream_t s);
 
 // Column-major FP64 matrix-core GEMM (k_dgemm.hip), strided batches:
 // C_b = alpha op(A_b) op(B_b) + beta C_b with op(A)(m, k) = ta ? A[k + m lda]
-// : A[m + k lda], op(B)(k, n) = tb ? B[n + k ldb] : B[k + n ldb].
+// : A[m + k lda], op(B)(k, n) = tb ? B[n + k ldb] : B[k + n ldb]; tile = 64
+// or 128 (the output tile edge of a workgroup).
 hipError_t launch_dgemm(bool ta, bool tb, int m, int n, int k, double alpha, const double *A, int64_t lda,
                         int64_t sA, const double *B, int64_t ldb, int64_t sB, double beta, double *C,
-                        int64_t ldc, int64_t sC, int batch, hipStream_t s);
+                        int64_t ldc, int64_t sC, int batch, hipStream_t s, int tile = 128);
+// The square m x m product C = op(A) op(B) (k deep) on and below its
+// diagonal only, stored as u2-major pairs: P_b[n m - n (n - 1) / 2 + (m' - n)]
+// = C(m', n) for m' >= n (sP >= m (m + 1) / 2 doubles per batch).
+hipError_t launch_dgemm_packed_lower(bool ta, bool tb, int m, int k, const double *A, int64_t lda, int64_t sA,
+                                     const double *B, int64_t ldb, int64_t sB, double *P, int64_t sP, int batch,
+                                     hipStream_t s);
 
 // Blocked Cholesky pieces (k_chol.hip): factor one diagonal block (at most
 // chol_block() wide; *info = 1 if it is not positive definite), and solve

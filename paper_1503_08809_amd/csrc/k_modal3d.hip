@@ -20,8 +20,9 @@
 // u1 below the end of each 128-wide block of u2 (u1 <= u2 <= u3 is read).
 // The l index is stored parity-sorted (even l first): for a given l1, K is
 // non-zero only where l1 + l2 + l3 is even, so stage 1 is two dense products
-// of half size (one per parity of l2).  The three stages are plain GEMMs
-// (rocBLAS); this file holds the operand builders and the gather.
+// of half size (one per parity of l2).  The three stages run on the FP64
+// matrix-core GEMM (k_dgemm.hip; stage 2 in its packed-triangle form); this
+// file holds the operand builders and the gather.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -152,30 +153,6 @@ __device__ __forceinline__ int64_t pair3(int U, int u2, int u3)
     return (int64_t)u2 * U - (int64_t)u2 * (u2 - 1) / 2 + (u3 - u2);
 }
 
-// P[rb NT + pair3(u2, u3)] = B[rb U^2 + u2 + U u3] for u2 <= u3, through
-// 32 x 32 tiles in LDS: read along u2 (contiguous in B), written along u3
-// (contiguous in P).  Block (32, 8); grid x = tile pairs (t2, t3), y = r.
-__global__ void k_pack3(int U, int ntile, const double *__restrict__ B, double *__restrict__ P)
-{
-    __shared__ double tile[32][33];
-    const int t2 = blockIdx.x % ntile, t3 = blockIdx.x / ntile;
-    if (t2 > t3) return;                                    // only tiles holding u2 <= u3
-    const int rb = blockIdx.y, tx = threadIdx.x, ty = threadIdx.y;
-    const int64_t NT = (int64_t)U * (U + 1) / 2;
-    const double *Br = B + (int64_t)rb * U * U;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int u2 = 32 * t2 + tx, u3 = 32 * t3 + ty + 8 * j;
-        tile[ty + 8 * j][tx] = (u2 < U && u3 < U) ? Br[u2 + (int64_t)U * u3] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int u2 = 32 * t2 + ty + 8 * j, u3 = 32 * t3 + tx;
-        if (u2 <= u3 && u3 < U) P[(int64_t)rb * NT + pair3(U, u2, u3)] = tile[tx][ty + 8 * j];
-    }
-}
-
 // Zero rows [row0, row0 + nrows) of every column of a column-major matrix
 // with leading dimension ld and ncols columns.
 __global__ void k_zero_rows3(int64_t ld, int row0, int nrows, int64_t ncols, double *__restrict__ A)
@@ -253,14 +230,6 @@ hipError_t launch_zero_rows3(int64_t ld, int row0, int nrows, int64_t ncols, dou
     if (n <= 0) return hipSuccess;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_rows3, dim3(blocks), dim3(256), 0, s, ld, row0, nrows, ncols, A);
-    return hipGetLastError();
-}
-
-hipError_t launch_pack3(int U, int nrb, const double *B, double *P, hipStream_t s)
-{
-    const int ntile = (U + 31) / 32;
-    if (nrb <= 0 || ntile <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack3, dim3(ntile * ntile, nrb), dim3(32, 8), 0, s, U, ntile, B, P);
     return hipGetLastError();
 }
 

@@ -92,8 +92,8 @@ def test_3d_single_l(mp, ctx, oracle, l):
 
 def _batch_bytes_per_r(L, U):
     """Bytes of Eq. (3D)'s batch operands per radial point (the header's
-    formula: 8 (2 L U + U^2 + U (U + 1) / 2 + U))."""
-    return 8 * (2 * L * U + U * U + U * (U + 1) // 2 + U)
+    formula: 8 (2 L U + U (U + 1) / 2 + U))."""
+    return 8 * (2 * L * U + U * (U + 1) // 2 + U)
 
 
 @pytest.mark.parametrize("threej", ["exact", "gosper"])
