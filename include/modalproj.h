@@ -259,6 +259,28 @@ modal_status modal_gram(modal_ctx ctx, const modal_grid *grid, const modal_probl
 modal_status modal_gamma_modal(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
                                modal_precision prec, double *gamma);
 
+/* The size in bytes of the device scratch array behind modal_gamma_noalloc
+ * (one per device, held until the process ends). */
+#define MODAL_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): Gamma
+ * exactly as modal_gamma computes it (same kernels, same results), with
+ * every intermediate buffer and plan taken from a fixed device scratch array
+ * of MODAL_NOALLOC_SCRATCH_BYTES per device instead of the context's
+ * workspace; the call makes no hipMalloc or hipFree (nor any allocating
+ * library call).  Every array, gamma included, must be device memory of the
+ * context's device (MODAL_ERR_INVALID_ARG otherwise: a host array would need
+ * staging).  A problem whose buffers do not fit in the scratch is refused
+ * with MODAL_ERR_OOM before its triple product runs (modal_gamma takes any
+ * size); the lmax = 64, 512 x 512 workload fits in either precision.  Stage
+ * timing is not recorded, and the adjoint cannot reuse this call's tables.
+ * All calls on one device share its scratch, which keeps the last call's
+ * contents: calls that overlap on one device (other contexts, other streams)
+ * race.  Validation still reads C_l and the mode lists back to the host. */
+modal_status modal_gamma_noalloc(modal_ctx ctx, const modal_grid *grid, const modal_problem *prob,
+                                 modal_precision prec, double *gamma);
+
 /* Gamma' of Eq. (3D) (Modal3D): the direct sum over l-triples with the
  * weight h^2 of Sec. 2.1 (Eq. (weight-function)) taken from the Wigner symbol
  * itself, MODAL_3J_EXACT (exact, by a product recurrence in FP64), or from

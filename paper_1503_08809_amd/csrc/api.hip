@@ -9,9 +9,22 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 
 using namespace mp;
+
+// ---- the no-allocation scratch ---------------------------------------------
+// modal_gamma_noalloc serves every buffer it needs from this array instead of
+// hipMalloc.  Each device holds its own copy, whose device address is looked
+// up once per device (modal_create) and kept in g_scratch_ptr; host code only
+// ever uses that address, never the array's name.  Calls on one device share
+// it: two such calls that overlap on one device race.
+constexpr size_t kScratchBytes = (size_t)MODAL_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices] = {};
 
 namespace {
 
@@ -86,6 +99,14 @@ struct modal_ctx_s {
     // to the last call (chunked stages record one pair per chunk)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MODAL_NSTAGES];
     int used[MODAL_NSTAGES] = {};
+    // no-allocation mode (modal_gamma_noalloc): every workspace slot and plan
+    // comes from the device's scratch array through a bump arena
+    bool arena_on = false;
+    DevArena arena;
+    void *aslot_p[NSLOTS] = {};
+    size_t aslot_n[NSLOTS] = {};
+    TriplePlan aplan64;                // plans built in the arena (borrowed)
+    BTPlan aplanbt;
 };
 
 namespace {
@@ -118,8 +139,19 @@ size_t held_bytes(modal_ctx c)
 
 void *ws_get(modal_ctx c, int slot, size_t bytes)
 {
-    Buf &b = c->ws[slot];
     if (bytes == 0) bytes = 8;
+    if (c->arena_on) {
+        if (c->aslot_n[slot] >= bytes) return c->aslot_p[slot];
+        void *p = nullptr;
+        if (c->arena.take(&p, bytes) != hipSuccess)
+            fail(c, MODAL_ERR_OOM,
+                 "the problem needs more than the " + std::to_string(kScratchBytes) +
+                     "-byte no-allocation scratch (use modal_gamma)");
+        c->aslot_p[slot] = p;
+        c->aslot_n[slot] = bytes;
+        return p;
+    }
+    Buf &b = c->ws[slot];
     if (b.n >= bytes) return b.p;
     if (c->limit && held_bytes(c) - b.n + bytes > c->limit)
         fail(c, MODAL_ERR_OOM, "workspace limit exceeded (" + std::to_string(bytes) + " bytes requested)");
@@ -162,6 +194,8 @@ const T *dev_in(modal_ctx c, const T *p, size_t count)
 {
     if (!p || count == 0) return p;
     if (is_device_ptr(c, p)) return p;
+    if (c->arena_on)
+        fail(c, MODAL_ERR_INVALID_ARG, "modal_gamma_noalloc takes device arrays only (a host array needs staging)");
     if (c->next_in >= 16) fail(c, MODAL_ERR_INVALID_ARG, "too many host inputs");
     T *d = (T *)ws_get(c, W_IN0 + c->next_in++, sizeof(T) * count);
     hipck(c, hipMemcpyAsync(d, p, sizeof(T) * count, hipMemcpyHostToDevice, c->stream), "H2D");
@@ -199,6 +233,8 @@ OutBuf dev_out(modal_ctx c, double *p, size_t count, int slot)
     if (is_device_ptr(c, p)) {
         o.dev = p;
     } else {
+        if (c->arena_on)
+            fail(c, MODAL_ERR_INVALID_ARG, "modal_gamma_noalloc takes device arrays only (a host output needs staging)");
         o.host = p;
         o.dev = (double *)ws_get(c, slot, sizeof(double) * count);
     }
@@ -220,7 +256,7 @@ struct StageTimer {
     hipEvent_t end = nullptr;
     StageTimer(modal_ctx c_, int s) : c(c_), st(s)
     {
-        if (!c->timing) return;
+        if (!c->timing || c->arena_on) return;      // events are not made in no-allocation mode
         auto &pool = c->ev[st];
         if (c->used[st] == (int)pool.size()) {
             hipEvent_t a = nullptr, b = nullptr;
@@ -533,6 +569,16 @@ Forward run_forward(modal_ctx c, const modal_grid *g, const modal_problem *p, co
 
 const TriplePlan &ensure_plan64(modal_ctx c, int U)
 {
+    if (c->arena_on) {          // built in the scratch for this call only
+        int rb, tpg, gr;
+        triple_f64_shape(rb, tpg, gr);
+        std::string err;
+        hipck(c, hipStreamSynchronize(c->stream), "sync");
+        hipError_t e = build_triple_plan(U, rb, tpg, gr, c->aplan64, err, &c->arena);
+        if (e != hipSuccess)
+            fail(c, e == hipErrorOutOfMemory ? MODAL_ERR_OOM : MODAL_ERR_DEVICE, err + " (no-allocation scratch)");
+        return c->aplan64;
+    }
     TriplePlan &pl = c->plan64;
     if (pl.U == U && pl.tasks) return pl;
     int rb, tpg, gr;
@@ -546,6 +592,14 @@ const TriplePlan &ensure_plan64(modal_ctx c, int U)
 
 const BTPlan &ensure_planbt(modal_ctx c, int U)
 {
+    if (c->arena_on) {          // built in the scratch for this call only
+        std::string err;
+        hipck(c, hipStreamSynchronize(c->stream), "sync");
+        hipError_t e = build_bt_plan(U, c->aplanbt, err, &c->arena);
+        if (e != hipSuccess)
+            fail(c, e == hipErrorOutOfMemory ? MODAL_ERR_OOM : MODAL_ERR_DEVICE, err + " (no-allocation scratch)");
+        return c->aplanbt;
+    }
     BTPlan &pl = c->planbt;
     if (pl.U == U && pl.tasks) return pl;
     std::string err;
@@ -862,6 +916,19 @@ modal_status modal_create(modal_ctx *out, int device, void *hip_stream)
         g_last_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
         return MODAL_ERR_DEVICE;
     }
+    {
+        // the device address of this device's scratch array, once per device
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (device < kMaxScratchDevices && !g_scratch_ptr[device]) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                g_last_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+                return MODAL_ERR_DEVICE;
+            }
+            g_scratch_ptr[device] = p;
+        }
+    }
     modal_ctx c = new (std::nothrow) modal_ctx_s;
     if (!c) {
         g_last_error = "host allocation failed";
@@ -1152,6 +1219,38 @@ modal_status modal_gamma(modal_ctx c, const modal_grid *g, const modal_problem *
         run_triple_gather(c, p, d, prec, f.St, o.dev);
         finish_out(c, o);
         c->fwd = FwdCache{true, false, *g, *p, f, fwd_in};
+    });
+}
+
+modal_status modal_gamma_noalloc(modal_ctx c, const modal_grid *g, const modal_problem *p, modal_precision prec,
+                                 double *gamma)
+{
+    return guarded(c, [&] {
+        void *base = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_scratch_mu);
+            if (c->device < kMaxScratchDevices) base = g_scratch_ptr[c->device];
+        }
+        need(c, base != nullptr, MODAL_ERR_DEVICE, "no no-allocation scratch on this device");
+        // arena mode for this call only (also on an error exit)
+        struct Scope {
+            modal_ctx c;
+            ~Scope() { c->arena_on = false; }
+        } scope{c};
+        c->arena = DevArena{(char *)base, kScratchBytes, 0};
+        for (int i = 0; i < NSLOTS; ++i) {
+            c->aslot_p[i] = nullptr;
+            c->aslot_n[i] = 0;
+        }
+        c->arena_on = true;
+        check_prec(c, prec);
+        Dims d = check_grid(c, g, true);
+        check_problem(c, p, d, true, true);
+        need(c, gamma != nullptr || (int64_t)p->ta * p->tp == 0, MODAL_ERR_INVALID_ARG, "gamma is NULL");
+        OutBuf o = dev_out(c, gamma, (size_t)p->ta * p->tp, W_GAMMA);
+        Forward f = run_forward(c, g, p, d);
+        run_triple_gather(c, p, d, prec, f.St, o.dev);
+        // the forward tables live in the shared scratch: never kept for reuse
     });
 }
 

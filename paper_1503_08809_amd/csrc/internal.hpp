@@ -25,6 +25,23 @@ struct Error {
     std::string msg;
 };
 
+// A bump allocator over caller-provided device memory: the no-allocation
+// entry point serves its workspace and plans from it instead of hipMalloc.
+struct DevArena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    // p = the next `bytes` (256-byte aligned); hipErrorOutOfMemory when the
+    // arena is full
+    hipError_t take(void **p, size_t bytes)
+    {
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (bytes > cap || off > cap - bytes) return hipErrorOutOfMemory;
+        *p = base + off;
+        used = off + bytes;
+        return hipSuccess;
+    }
+};
+
 // ---- launchers (one per kernel family) --------------------------------
 // Step a: grids and tables.
 hipError_t launch_gauss_legendre(int n, double *x, double *w, hipStream_t s);
@@ -95,13 +112,15 @@ struct TriplePlan {
     unsigned short *pair_lj = nullptr; // [ntiles * 16] local row of j in its group
     unsigned short *pair_lk = nullptr; // [ntiles * 16]
     int2 *tasks = nullptr;       // [ntasks] (group, row super-block)
+    bool borrowed = false;       // arrays live in a DevArena (never freed)
 };
 // S rows are allocated padded to a multiple of kRowPad (>= every rowblock),
 // and the z blocks of 32 to a multiple of kZBlockPad (zero past the data).
 constexpr int kRowPad = 256;
 constexpr int kZBlockPad = 8;
+// arena != NULL: the plan's device arrays are taken from it (no hipMalloc)
 hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group_rows,
-                             TriplePlan &plan, std::string &err);
+                             TriplePlan &plan, std::string &err, DevArena *arena = nullptr);
 void free_triple_plan(TriplePlan &plan);
 // shape of the FP64 kernel
 void triple_f64_shape(int &rowblock, int &tiles_per_group, int &group_rows);
@@ -121,8 +140,9 @@ struct BTPlan {
     int64_t tsize = 0;         // doubles of T
     int4 *tasks = nullptr;     // device [ntasks]
     int *tidx = nullptr;       // device [nib][njb][nkb]
+    bool borrowed = false;     // arrays live in a DevArena (never freed)
 };
-hipError_t build_bt_plan(int U, BTPlan &plan, std::string &err);
+hipError_t build_bt_plan(int U, BTPlan &plan, std::string &err, DevArena *arena = nullptr);
 void free_bt_plan(BTPlan &plan);
 hipError_t launch_triple_bt(const BTPlan &plan, int64_t upad, int64_t ldz, int nmu_pad,
                             const float *S32, const uint16_t *SA, double *T, hipStream_t s);

@@ -291,7 +291,7 @@ void triple_f64_shape(int &rb, int &tpg, int &gr)
 }
 
 hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group_cap,
-                             TriplePlan &plan, std::string &err)
+                             TriplePlan &plan, std::string &err, DevArena *arena)
 {
     free_triple_plan(plan);
     plan.U = U;
@@ -372,12 +372,14 @@ hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group
     // runs) share their 128 A rows, and neighbouring groups part of their rows
     std::stable_sort(tasks.begin(), tasks.end(), [](int2 a, int2 b) { return a.y < b.y; });
     plan.ntasks = (int)tasks.size();
+    plan.borrowed = arena != nullptr;
 
     hipError_t e = hipSuccess;
     auto up = [&](auto *&dst, const auto &src) {
         using T = std::remove_cv_t<std::remove_reference_t<decltype(src[0])>>;
         if (e != hipSuccess) return;
-        e = hipMalloc((void **)&dst, sizeof(T) * std::max<size_t>(src.size(), 1));
+        const size_t nb = sizeof(T) * std::max<size_t>(src.size(), 1);
+        e = arena ? arena->take((void **)&dst, nb) : hipMalloc((void **)&dst, nb);
         if (e == hipSuccess && !src.empty())
             e = hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
     };
@@ -398,6 +400,10 @@ hipError_t build_triple_plan(int U, int rowblock, int tiles_per_group, int group
 
 void free_triple_plan(TriplePlan &p)
 {
+    if (p.borrowed) {
+        p = TriplePlan{};
+        return;
+    }
     (void)hipFree(p.tile_maxj);
     (void)hipFree(p.tile_off);
     (void)hipFree(p.group_tile0);

@@ -324,7 +324,7 @@ __global__ void k_gather_bt(int kind, int ta, int tp, const int *__restrict__ tr
 
 }  // namespace
 
-hipError_t build_bt_plan(int U, BTPlan &plan, std::string &err)
+hipError_t build_bt_plan(int U, BTPlan &plan, std::string &err, DevArena *arena)
 {
     free_bt_plan(plan);
     plan.U = U;
@@ -345,10 +345,12 @@ hipError_t build_bt_plan(int U, BTPlan &plan, std::string &err)
         }
     plan.ntasks = (int)tasks.size();
     plan.tsize = (int64_t)plan.ntasks * TASK_SIZE;
-    hipError_t e = hipMalloc((void **)&plan.tasks, sizeof(int4) * std::max<size_t>(tasks.size(), 1));
+    plan.borrowed = arena != nullptr;
+    auto get = [&](void **p, size_t nb) { return arena ? arena->take(p, nb) : hipMalloc(p, nb); };
+    hipError_t e = get((void **)&plan.tasks, sizeof(int4) * std::max<size_t>(tasks.size(), 1));
     if (e == hipSuccess && !tasks.empty())
         e = hipMemcpy(plan.tasks, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void **)&plan.tidx, sizeof(int) * tidx.size());
+    if (e == hipSuccess) e = get((void **)&plan.tidx, sizeof(int) * tidx.size());
     if (e == hipSuccess)
         e = hipMemcpy(plan.tidx, tidx.data(), sizeof(int) * tidx.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -360,6 +362,10 @@ hipError_t build_bt_plan(int U, BTPlan &plan, std::string &err)
 
 void free_bt_plan(BTPlan &p)
 {
+    if (p.borrowed) {
+        p = BTPlan{};
+        return;
+    }
     (void)hipFree(p.tasks);
     (void)hipFree(p.tidx);
     p = BTPlan{};

@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "modal_S": [vp, G, P, ctypes.c_int, vp, vp],
             "modal_gamma_from_S": [vp, G, P, ctypes.c_int, vp, vp],
             "modal_gamma": [vp, G, P, ctypes.c_int, vp],
+            "modal_gamma_noalloc": [vp, G, P, ctypes.c_int, vp],
             "modal_gram": [vp, G, P, ctypes.c_int, vp],
             "modal_gamma_modal": [vp, G, P, ctypes.c_int, vp],
             "modal_gamma_backward": [vp, G, P, ctypes.c_int, vp, vp, vp],
@@ -110,7 +111,7 @@ def exported_symbols():
             "modal_gauss_legendre",
             "modal_legendre_table", "modal_sph_bessel_table", "modal_beta", "modal_S",
             "modal_gamma_from_S", "modal_gamma", "modal_gram", "modal_gamma_modal",
-            "modal_gamma_backward", "modal_r_weights", "modal_gamma_3d"]
+            "modal_gamma_backward", "modal_r_weights", "modal_gamma_3d", "modal_gamma_noalloc"]
 
 
 def _ptr(x) -> Optional[int]:
@@ -355,6 +356,15 @@ class Projection:
                                          _PREC[precision], out.data_ptr()))
         return out
 
+    def gamma_noalloc(self, precision: str = "fp64", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Gamma through modal_gamma_noalloc: no device allocation in the
+        library (its buffers come from a fixed per-device scratch array)."""
+        g, p = self.structs()
+        if out is None:
+            out = self.ctx.empty(self.tri_a.shape[0], self.tri_p.shape[0])
+        self.ctx.check(lib().modal_gamma_noalloc(self.ctx.handle, ctypes.byref(g), ctypes.byref(p),
+                                                 _PREC[precision], out.data_ptr()))
+        return out
 
     def gram(self, precision: str = "fp64") -> torch.Tensor:
         """The late-time Gram matrix <Q_n, Q_m> over tri_a x tri_a."""
