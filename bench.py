@@ -8,7 +8,8 @@ regenerated, not stored).  Inputs are seeded synthetic tables already
 resident in HBM.  Prints ONE JSON line.  The default workload is the
 Planck-like case: lmax = 2500, Nk = 2000, Nr = 400, Nmu = 3752, 30 + 30
 one-dimensional modes, symmetric 4960 x 4960 Gamma, in the mixed precision;
-the FP64 path runs one step beside it for the speed-up and the errors.
+the FP64 path runs beside it (one untimed and three timed steps by default)
+for the speed-up and the errors.
 
 Fields beyond the driver contract:
   roofline      the dominant kernel of the timed path (the adjoint of the
@@ -23,8 +24,19 @@ Fields beyond the driver contract:
   cpu_baseline  the oracle (plain FP64 C, OpenMP) timed on this host on a
                 bounded sample of the same workload, extrapolated by its
                 exact per-unit costs.
-  paths         per-precision seconds per step, forward and adjoint
-                separately, per-stage milliseconds, errors vs the FP64 path.
+  paths         per-precision seconds per step (mean over the timed steps,
+                and their median), forward and adjoint separately,
+                per-stage milliseconds, errors vs the FP64 path.  The FP64
+                path runs --fp64-warmup untimed and --fp64-steps timed steps.
+
+Other modes (their own JSON line, not the benchmark line):
+  --modal3d     times Eq. (3D) (modal_gamma_3d, exact symbol) on the
+                workload: seconds per call, algorithmic TFLOP/s against the
+                FP64 peak, the normwise error against Eq. (2D) in FP64, and
+                the error on the stored oracle rows when there are some.
+  --cpu-full    times the whole oracle (every stage, every Gamma entry, and
+                the adjoint unless --forward-only) on this host: the small
+                workloads only.
 """
 from __future__ import annotations
 
@@ -95,6 +107,40 @@ def measured_traffic(kernel: str, tag: str):
     return None
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and logical core count."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def cpu_full(inp, adjoint: bool) -> dict:
+    """The whole oracle on this host: Gamma in full (every stage, every
+    entry) and, with the adjoint, dL/dq and dL/dDelta for dL/dGamma = 2
+    Gamma W^2 (the benchmark's loss).  Small workloads only."""
+    from oracle import oracle as O
+    from paper_1503_08809_amd import synth
+    c = inp.cfg
+    t0 = time.perf_counter()
+    g = O.gamma_full(inp)
+    t = {"gamma": time.perf_counter() - t0}
+    if adjoint:
+        W = synth.loss_weights(c, g.shape[0], g.shape[1])
+        t0 = time.perf_counter()
+        O.gamma_full_backward(inp, 2.0 * g * W * W)
+        t["adjoint"] = time.perf_counter() - t0
+    out = {"value": sum(t.values()), "unit": "s", "cores": O.num_threads(), "kind": "oracle",
+           "sample": "the whole workload (not sampled)", "stages_s": t}
+    out.update(host_cpu())
+    return out
+
+
 def cpu_baseline(inp, adjoint: bool = True) -> dict:
     """Time the oracle on a bounded sample and extrapolate.
 
@@ -146,8 +192,63 @@ def cpu_baseline(inp, adjoint: bool = True) -> dict:
         t["adj_beta"] = (time.perf_counter() - t0) * rscale
         sample += "; the three adjoint stages on the same sample"
     sample += "; per-unit costs x unit counts (cost is linear in each)"
-    return {"value": sum(t.values()), "unit": "s (extrapolated)", "cores": O.num_threads(),
-            "kind": "oracle", "sample": sample, "stages_s": t}
+    out = {"value": sum(t.values()), "unit": "s (extrapolated)", "cores": O.num_threads(),
+           "kind": "oracle", "sample": sample, "stages_s": t}
+    out.update(host_cpu())
+    return out
+
+
+def modal3d_flops(cfg) -> float:
+    """Algorithmic FLOPs of Eq. (3D) as contracted here (an FMA counts 2):
+    stage 1 over the (l1, l2, l3) triples that meet the triangle and parity
+    conditions, for every r and row u; stage 2 one triangle of the symmetric
+    B_r per (l1, r); stage 3 the unique moments u1 <= u2 <= u3 per (l1, r)."""
+    ls = np.arange(cfg.lmin, cfg.lmax + 1)
+    L, U, nr = cfg.L, cfg.n1 * cfg.n1, cfg.nr
+    ntri = 0
+    for l1 in ls:
+        lo = np.abs(l1 - ls)
+        hi = np.minimum(l1 + ls, cfg.lmax)
+        first = np.maximum(lo, cfg.lmin)
+        first = first + ((l1 + ls + first) & 1)            # l3 of the parity of l1 + l2
+        ntri += int(np.maximum(0, (hi - first) // 2 + 1).sum())
+    return 2.0 * nr * U * ntri + float(L) * L * nr * U * (U + 1) + 2.0 * L * nr * unique_moments(U)
+
+
+def run_modal3d(cfg, inp, reps: int) -> dict:
+    """Eq. (3D) timed on the workload, checked against Eq. (2D) (FP64 path)
+    and against the stored oracle rows."""
+    import gzip
+    import torch
+    from paper_1503_08809_amd import modalproj as mp
+    ctx = mp.Context(0)
+    pr = mp.projection_from_inputs(ctx, inp)
+    g2 = pr.gamma("fp64")
+    times = []
+    for i in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g3 = pr.gamma_3d("exact")
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print(f"[bench] Eq. (3D) call {i + 1}/{reps}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    sec = float(np.mean(times))
+    fl = modal3d_flops(cfg)
+    out = {"mode": "modal3d", "workload": cfg.name, "s_per_call": sec, "median_s": float(np.median(times)),
+           "calls": reps, "algorithmic_tflop": fl / 1e12, "achieved_tflops": fl / sec / 1e12,
+           "frac_fp64_peak": fl / sec / 1e12 / PEAK_TFLOPS["fp64"],
+           "normwise_err_vs_eq2d_fp64": float((g3 - g2).abs().max() / g2.abs().max())}
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_rows_{cfg.name}.txt.gz")
+    if os.path.exists(path):
+        with gzip.open(path, "rt") as f:
+            a = np.loadtxt(f, comments="#", ndmin=2)
+        rows, cols = a[:, 0].astype(np.int64), a[:, 1].astype(np.int64)
+        g = g3.cpu().numpy()[rows, cols]
+        out["stored_rows_entries"] = int(rows.size)
+        out["stored_rows_err_over_scale"] = float((np.abs(g - a[:, 2]) / a[:, 3]).max())
+        out["stored_rows_normwise_err"] = float(np.abs(g - a[:, 2]).max() / float(g2.abs().max()))
+    ctx.close()
+    return out
 
 
 def measure_ceilings() -> dict:
@@ -203,6 +304,12 @@ def main() -> int:
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--ceilings", action="store_true",
                     help="measure library GEMM and copy ceilings on this GPU, print them, exit")
+    ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the FP64 reference path")
+    ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed steps of the FP64 reference path")
+    ap.add_argument("--modal3d", type=int, default=0, metavar="CALLS",
+                    help="time Eq. (3D) (modal_gamma_3d) over this many calls on the workload, print, exit")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the whole oracle on this host (small workloads), print, exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -221,6 +328,17 @@ def main() -> int:
     inp = synth.make_inputs(cfg)
     print(f"[bench] inputs for {cfg.name} in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
           flush=True)
+    if args.cpu_full:
+        if cfg.lmax > 500:
+            print("bench.py: --cpu-full runs the whole oracle; use it on lmax <= 500", file=sys.stderr)
+            return 2
+        res = cpu_full(inp, not args.forward_only)
+        res.update({"mode": "cpu_full", "workload": cfg.name})
+        print(json.dumps(res))
+        return 0
+    if args.modal3d:
+        print(json.dumps(run_modal3d(cfg, inp, args.modal3d)))
+        return 0
     ctx = mp.Context(0)
     # the inputs never change: the adjoint takes the forward's tables (steps
     # a-c) instead of recomputing them, as an autograd backward would
@@ -267,11 +385,13 @@ def main() -> int:
         acc = {"fwd": 0.0, "adj": 0.0}
         stf, stb = {}, {}
         grads = None
+        per_step = []
         t_start = time.perf_counter()
         for s in range(steps):
             tf, tb, sf, sb, grads = one_step(prec, True)
             acc["fwd"] += tf
             acc["adj"] += tb
+            per_step.append(tf + tb)
             for src, dst in ((sf, stf), (sb, stb)):
                 for kname, v in (src or {}).items():
                     if v:
@@ -281,7 +401,8 @@ def main() -> int:
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         ctx.enable_timing(False)
-        res = {"s_per_step": elapsed / steps, "forward_s": acc["fwd"] / steps,
+        res = {"s_per_step": elapsed / steps, "median_s_per_step": float(np.median(per_step)),
+               "steps": steps, "warmup": warmup, "forward_s": acc["fwd"] / steps,
                "adjoint_s": acc["adj"] / steps,
                "stage_ms_forward": {k: v / steps for k, v in stf.items()},
                "stage_ms_adjoint": {k: v / steps for k, v in stb.items()}}
@@ -303,8 +424,8 @@ def main() -> int:
     main_prec = args.precision
     ref = None
     if main_prec == "fp64" or not args.no_fp64_ref:
-        fp_steps = args.steps if main_prec == "fp64" else 1
-        fp_warm = args.warmup if main_prec == "fp64" else 0
+        fp_steps = args.steps if main_prec == "fp64" else max(1, args.fp64_steps)
+        fp_warm = args.warmup if main_prec == "fp64" else max(0, args.fp64_warmup)
         paths["fp64"], g64 = run_path("fp64", fp_steps, fp_warm)
         ref = (out.clone(), g64)
     if main_prec == "mixed":
