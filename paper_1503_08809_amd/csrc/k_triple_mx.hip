@@ -25,12 +25,15 @@
 //
 // Eight waves (two per SIMD): wave w owns rows 32 (w % 4) .. + 31 of the
 // task and pair tiles 8 (w / 4) .. + 7.  Per 32-wide z step a wave issues
-// 2 row blocks x 8 pair tiles x 3 products = 48 matrix-core operations,
-// reading each pair tile from LDS two tiles ahead of its use; generates 2 of
-// the 16 pair tiles for the next step (its k rows read once for both) and
-// shares them through LDS (double-buffered, one barrier per step); loads its
-// A fragments straight from memory two steps ahead (two register sets); and
-// all threads stage the 32 source rows of the step after next.
+// 2 row blocks x 8 pair tiles x 3 products = 48 matrix-core operations, two
+// pair tiles at a time (12 operations ordered product by product, so that
+// dependent operations on one accumulator are four apart; 3 % faster than
+// one tile at a time, the same bits), reading the next two tiles from LDS
+// while the current two are multiplied; generates 2 of the 16 pair tiles for
+// the next step (its k rows read once for both) and shares them through LDS
+// (double-buffered, one barrier per step); loads its A fragments straight
+// from memory two steps ahead (two register sets); and all threads stage the
+// 32 source rows of the step after next.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -209,32 +212,48 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
             // tile j + 2 is read from LDS while tile j's 6 matrix-core
             // operations run; this wave's 2 pair tiles of step s + 1 are
             // generated after tiles 3 and 7 (VALU work under the matrix cores)
-            uint4 bh = Bb[buf][th * TW][0][lane], bl = Bb[buf][th * TW][1][lane];
-            uint4 mbh = Bb[buf][th * TW + 1][0][lane], mbl = Bb[buf][th * TW + 1][1][lane];
+            // pairs of pair tiles: the operands of pair p + 1 are read while
+            // pair p's 12 matrix-core operations run, ordered product by
+            // product over both tiles and both row blocks so that dependent
+            // operations on one accumulator are four apart
+            uint4 ch[2], cl[2], nh[2], nl[2];
 #pragma unroll
-            for (int j = 0; j < TW; ++j) {
-                uint4 nbh = mbh, nbl = mbl;
-                if (j + 2 < TW) {
-                    nbh = Bb[buf][th * TW + j + 2][0][lane];
-                    nbl = Bb[buf][th * TW + j + 2][1][lane];
+            for (int q = 0; q < 2; ++q) {
+                ch[q] = Bb[buf][th * TW + q][0][lane];
+                cl[q] = Bb[buf][th * TW + q][1][lane];
+            }
+#pragma unroll
+            for (int p = 0; p < TW / 2; ++p) {
+                if (p + 1 < TW / 2) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        nh[q] = Bb[buf][th * TW + 2 * p + 2 + q][0][lane];
+                        nl[q] = Bb[buf][th * TW + 2 * p + 2 + q][1][lane];
+                    }
                 }
-                const bf8 h8 = as_bf8(bh), l8 = as_bf8(bl);
 #pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), h8, acc[i][j], 0, 0, 0);
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), l8, acc[i][j], 0, 0, 0);
+                    for (int i = 0; i < RB; ++i)
+                        acc[i][2 * p + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), as_bf8(ch[q]), acc[i][2 * p + q], 0, 0, 0);
 #pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), h8, acc[i][j], 0, 0, 0);
-                if (j == 3) bgen_k(buf ^ 1);
-                if ((j & 3) == 3) bgen_tile(buf ^ 1, j >> 2);      // operand of step s + 1
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        acc[i][2 * p + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), as_bf8(cl[q]), acc[i][2 * p + q], 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        acc[i][2 * p + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), as_bf8(ch[q]), acc[i][2 * p + q], 0, 0, 0);
+                if (p == 1) bgen_k(buf ^ 1);
+                if ((p & 1) == 1) bgen_tile(buf ^ 1, p >> 1);      // operand of step s + 1
                 __builtin_amdgcn_sched_barrier(0);
-                bh = mbh;
-                bl = mbl;
-                mbh = nbh;
-                mbl = nbl;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    ch[q] = nh[q];
+                    cl[q] = nl[q];
+                }
             }
         } else {
             bgen_k(buf ^ 1);
