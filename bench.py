@@ -166,10 +166,12 @@ def cpu_baseline(inp, adjoint: bool = True) -> dict:
     t0 = time.perf_counter()
     bet = O.beta(sub)                                   # every primordial mode
     t["beta"] = (time.perf_counter() - t0) * rscale
+    print("[bench] oracle sample stage beta done", file=sys.stderr, flush=True)
     pairs = [(a, p) for a in range(min(c.n1, 3)) for p in range(min(c.n1, 3))]
     t0 = time.perf_counter()
     S = O.S_pairs(sub, mu, bet, pairs)
     t["S"] = (time.perf_counter() - t0) / len(pairs) * U * rscale
+    print("[bench] oracle sample stage S done", file=sys.stderr, flush=True)
     ne = 1 << 16
     rng = np.random.default_rng(0)
     sidx = rng.integers(0, len(pairs), size=(ne, 9)).astype(np.int32)
@@ -177,6 +179,7 @@ def cpu_baseline(inp, adjoint: bool = True) -> dict:
     t0 = time.perf_counter()
     O.gamma_from_S(sub, wmu, S, sidx)
     t["gamma"] = (time.perf_counter() - t0) / ne * n_entries * rscale
+    print("[bench] oracle sample stage gamma done", file=sys.stderr, flush=True)
     sample = (f"oracle stages on {nr_s} of {c.nr} r points: beta for all modes, "
               f"S for {len(pairs)} of {U} (a,p) pairs, {ne} of {n_entries} Gamma entries")
     if adjoint:
@@ -184,9 +187,11 @@ def cpu_baseline(inp, adjoint: bool = True) -> dict:
         t0 = time.perf_counter()
         Shat = O.gamma_adjoint_S(sub, wmu, S, sidx, g)
         t["adj_gamma"] = (time.perf_counter() - t0) / ne * n_entries * rscale
+        print("[bench] oracle sample stage adj_gamma done", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         bhat = O.S_adjoint(sub, mu, Shat, np.array(pairs, dtype=np.int32), c.n1)
         t["adj_S"] = (time.perf_counter() - t0) / len(pairs) * U * rscale
+        print("[bench] oracle sample stage adj_S done", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         O.beta_adjoint(sub, bhat)
         t["adj_beta"] = (time.perf_counter() - t0) * rscale
@@ -306,6 +311,10 @@ def main() -> int:
                     help="measure library GEMM and copy ceilings on this GPU, print them, exit")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed steps of the FP64 reference path")
     ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed steps of the FP64 reference path")
+    ap.add_argument("--fp64-adjoint-chunks", type=int, default=1, metavar="N",
+                    help="run the FP64 adjoint as N calls on consecutive r-chunks of the grid, summed (for a "
+                         "fixed dL/dGamma the gradient is a sum over r); each call then finishes in 1/N of the "
+                         "time, and steps a-c are recomputed per chunk")
     ap.add_argument("--modal3d", type=int, default=0, metavar="CALLS",
                     help="time Eq. (3D) (modal_gamma_3d) over this many calls on the workload, print, exit")
     ap.add_argument("--cpu-full", action="store_true",
@@ -360,6 +369,30 @@ def main() -> int:
               file=sys.stderr, flush=True)
         del src, dst
 
+    # the FP64 adjoint in r-chunks: projections on consecutive slices of the
+    # r grid with the same per-node weights
+    chunks = []
+    if args.fp64_adjoint_chunks > 1:
+        for idx in np.array_split(np.arange(cfg.nr), args.fp64_adjoint_chunks):
+            chunks.append(mp.projection_from_inputs(ctx, inp, r=inp.r[idx].copy(), wr=inp.wr[idx].copy()))
+
+    def backward(prec: str, dG, timed: bool):
+        if prec != "fp64" or not chunks:
+            g = pr.gamma_backward(dG, prec)
+            return g, (ctx.stage_times() if timed else None)
+        dq = dd = None
+        st = {}
+        for ci, prc in enumerate(chunks):
+            tq = time.perf_counter()
+            a, b = prc.gamma_backward(dG, prec)
+            sc = ctx.stage_times()                          # waits for the stream
+            dq, dd = (a, b) if dq is None else (dq + a, dd + b)
+            for kname, v in sc.items():
+                st[kname] = st.get(kname, 0.0) + v
+            print(f"[bench] fp64 adjoint chunk {ci + 1}/{len(chunks)} ({prc.r.numel()} r): "
+                  f"{time.perf_counter() - tq:.3f} s", file=sys.stderr, flush=True)
+        return (dq, dd), (st if timed else None)
+
     def one_step(prec: str, timed: bool):
         ta = time.perf_counter()
         pr.gamma(prec, out=out)
@@ -367,10 +400,10 @@ def main() -> int:
         if not timed:
             torch.cuda.synchronize()
         tb = time.perf_counter()
+        print(f"[bench] {prec} forward {tb - ta:.3f} s", file=sys.stderr, flush=True)
         grads, sb = None, None
         if adjoint:
-            grads = pr.gamma_backward(out * W2, prec)
-            sb = ctx.stage_times() if timed else None
+            grads, sb = backward(prec, out * W2, timed)
             if not timed:
                 torch.cuda.synchronize()
         tc = time.perf_counter()
