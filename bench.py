@@ -128,7 +128,19 @@ def cpu_full(inp, adjoint: bool) -> dict:
     from paper_1503_08809_amd import synth
     c = inp.cfg
     t0 = time.perf_counter()
-    g = O.gamma_full(inp)
+    # the oracle's Gamma in full, its rows in blocks (a progress line after each)
+    mu, wmu = O.gauss_legendre(c.nmu)
+    S, _ = O.full_S(inp, mu)
+    S = S.reshape(-1, c.nr, c.nmu)
+    npm = inp.qk.shape[0]
+    ta, tp = inp.tri_a, inp.tri_p
+    g = np.empty((ta.shape[0], tp.shape[0]))
+    nblk = 16
+    for bi, rows in enumerate(np.array_split(np.arange(ta.shape[0]), nblk)):
+        sidx = (ta[rows][:, None, :, None] * npm + tp[None, :, None, :]).reshape(-1, 9)
+        g[rows] = O.gamma_from_S(inp, wmu, S, sidx).reshape(rows.size, tp.shape[0])
+        print(f"[bench] oracle Gamma rows block {bi + 1}/{nblk}: {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     t = {"gamma": time.perf_counter() - t0}
     if adjoint:
         W = synth.loss_weights(c, g.shape[0], g.shape[1])
