@@ -208,14 +208,12 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
         sstore(buf);                                       // sources of step s + 2
         sload(s + 3 < last ? s + 3 : last);
         if (active) {
-            // software pipeline over this wave's 8 pair tiles: the operand of
-            // tile j + 2 is read from LDS while tile j's 6 matrix-core
-            // operations run; this wave's 2 pair tiles of step s + 1 are
-            // generated after tiles 3 and 7 (VALU work under the matrix cores)
             // pairs of pair tiles: the operands of pair p + 1 are read while
             // pair p's 12 matrix-core operations run, ordered product by
             // product over both tiles and both row blocks so that dependent
-            // operations on one accumulator are four apart
+            // operations on one accumulator are four apart; this wave's 2
+            // pair tiles of step s + 1 are generated after pairs 1 and 3
+            // (VALU work under the matrix cores)
             uint4 ch[2], cl[2], nh[2], nl[2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
