@@ -195,7 +195,12 @@ modal_status modal_stage_counts(modal_ctx ctx, int32_t *counts, int n);
 
 /* n-point Gauss-Legendre rule on [-1, 1] (Sec. 2.2: exact for the
  * polynomial mu integrand).  x ascending, x[i] = -x[n-1-i]; w > 0.
- * x, w: [n].  n >= 1. */
+ * x, w: [n].  n >= 1.  Each root is refined by Newton's method in
+ * double-double arithmetic and rounded once (nodes and weights correctly
+ * rounded to FP64).  With ctx == NULL the rule is computed on the host, into
+ * host arrays, by the same code (no context and no device needed; errors
+ * are read with modal_last_error(NULL)); otherwise on the context's device
+ * (host or device arrays, as everywhere). */
 modal_status modal_gauss_legendre(modal_ctx ctx, int32_t n, double *x, double *w);
 
 /* Legendre table P[l][j] = P_l(mu_j), l = 0..lmax, j < nmu (the P_l(mu) of

@@ -1079,6 +1079,24 @@ modal_status modal_workspace_bytes(modal_ctx c, const modal_grid *g, const modal
 
 modal_status modal_gauss_legendre(modal_ctx c, int32_t n, double *x, double *w)
 {
+    if (!c) {
+        // host rule, host arrays: no context and no device needed
+        if (n < 1) {
+            g_last_error = "n must be >= 1";
+            return MODAL_ERR_SHAPE;
+        }
+        if (!x || !w) {
+            g_last_error = "x, w must be non-NULL";
+            return MODAL_ERR_INVALID_ARG;
+        }
+        try {
+            gauss_legendre_host(n, x, w);
+        } catch (...) {
+            g_last_error = "host Gauss-Legendre rule failed (thread start)";
+            return MODAL_ERR_DEVICE;
+        }
+        return MODAL_OK;
+    }
     return guarded(c, [&] {
         need(c, n >= 1, MODAL_ERR_SHAPE, "n must be >= 1");
         need(c, x && w, MODAL_ERR_INVALID_ARG, "x, w must be non-NULL");

@@ -45,6 +45,8 @@ struct DevArena {
 // ---- launchers (one per kernel family) --------------------------------
 // Step a: grids and tables.
 hipError_t launch_gauss_legendre(int n, double *x, double *w, hipStream_t s);
+// The same rule computed on the host (host arrays, no device).
+void gauss_legendre_host(int n, double *x, double *w);
 hipError_t launch_legendre_table(int lmax, int lout0, int nmu, int ld, const double *mu,
                                  double *P, hipStream_t s);
 

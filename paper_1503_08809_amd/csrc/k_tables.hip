@@ -25,7 +25,10 @@
 // stored; chunks are consumed by the k contraction as they are made.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cmath>
+#include <thread>
+#include <vector>
 
 namespace mp {
 namespace {
@@ -41,22 +44,22 @@ namespace {
 struct dd {
     double hi, lo;
 };
-__device__ __forceinline__ dd two_sum(double a, double b)
+__host__ __device__ __forceinline__ dd two_sum(double a, double b)
 {
     const double s = a + b, bb = s - a;
     return {s, (a - (s - bb)) + (b - bb)};
 }
-__device__ __forceinline__ dd quick_two_sum(double a, double b)
+__host__ __device__ __forceinline__ dd quick_two_sum(double a, double b)
 {
     const double s = a + b;
     return {s, b - (s - a)};
 }
-__device__ __forceinline__ dd two_prod(double a, double b)
+__host__ __device__ __forceinline__ dd two_prod(double a, double b)
 {
     const double p = a * b;
     return {p, fma(a, b, -p)};
 }
-__device__ __forceinline__ dd dd_add(dd x, dd y)
+__host__ __device__ __forceinline__ dd dd_add(dd x, dd y)
 {
     dd s = two_sum(x.hi, y.hi), t = two_sum(x.lo, y.lo);
     s.lo += t.hi;
@@ -64,20 +67,20 @@ __device__ __forceinline__ dd dd_add(dd x, dd y)
     s.lo += t.lo;
     return quick_two_sum(s.hi, s.lo);
 }
-__device__ __forceinline__ dd dd_neg(dd x) { return {-x.hi, -x.lo}; }
-__device__ __forceinline__ dd dd_mul(dd x, dd y)
+__host__ __device__ __forceinline__ dd dd_neg(dd x) { return {-x.hi, -x.lo}; }
+__host__ __device__ __forceinline__ dd dd_mul(dd x, dd y)
 {
     dd p = two_prod(x.hi, y.hi);
     p.lo += x.hi * y.lo + x.lo * y.hi;
     return quick_two_sum(p.hi, p.lo);
 }
-__device__ __forceinline__ dd dd_mul_d(dd x, double d)
+__host__ __device__ __forceinline__ dd dd_mul_d(dd x, double d)
 {
     dd p = two_prod(x.hi, d);
     p.lo += x.lo * d;
     return quick_two_sum(p.hi, p.lo);
 }
-__device__ __forceinline__ dd dd_div(dd x, dd y)
+__host__ __device__ __forceinline__ dd dd_div(dd x, dd y)
 {
     const double q1 = x.hi / y.hi;
     dd r = dd_add(x, dd_neg(dd_mul_d(y, q1)));
@@ -89,7 +92,7 @@ __device__ __forceinline__ dd dd_div(dd x, dd y)
 }
 
 // P_n(z) and P_{n-1}(z) by the three-term recurrence, in double-double.
-__device__ void legendre_pair_dd(int n, dd z, dd &pn, dd &pn1)
+__host__ __device__ void legendre_pair_dd(int n, dd z, dd &pn, dd &pn1)
 {
     dd p0{1.0, 0.0}, p1 = z;
     for (int l = 1; l < n; ++l) {
@@ -108,15 +111,15 @@ __device__ void legendre_pair_dd(int n, dd z, dd &pn, dd &pn1)
     }
 }
 
-__global__ void k_gauss_legendre(int n, double *__restrict__ x, double *__restrict__ w)
+// The i-th largest root of P_n (i < (n + 1) / 2) and its weight; the same
+// code runs in the device kernel and in the host rule (modal_gauss_legendre
+// without a context).
+__host__ __device__ void gl_root(int n, int i, double &xr, double &wr)
 {
-    const int half = (n + 1) / 2;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // i-th largest root
-    if (i >= half) return;
     const double dn = (double)n;
     const double th = kPi * (4.0 * i + 3.0) / (4.0 * dn + 2.0);
     dd z{(1.0 - 1.0 / (8.0 * dn * dn) + 1.0 / (8.0 * dn * dn * dn)) * cos(th), 0.0};
-    const bool centre = (n % 2 == 1 && i == half - 1);
+    const bool centre = (n % 2 == 1 && i == (n + 1) / 2 - 1);
     if (centre) z = {0.0, 0.0};
     // FP64 Newton to ~1e-13 relative, then two double-double steps (quadratic
     // convergence: ~1e-26, then far below FP64 resolution).  The FP64 steps
@@ -157,7 +160,17 @@ __global__ void k_gauss_legendre(int n, double *__restrict__ x, double *__restri
     // w = 2 / ((1 - z^2) P_n'(z)^2)
     const dd omz2 = dd_mul(dd_add(one, dd_neg(z)), dd_add(one, z));
     const dd wv = dd_div(dd{2.0, 0.0}, dd_mul(omz2, dd_mul(dp, dp)));
-    const double zr = z.hi + z.lo, wi = wv.hi + wv.lo;
+    xr = z.hi + z.lo;
+    wr = wv.hi + wv.lo;
+}
+
+__global__ void k_gauss_legendre(int n, double *__restrict__ x, double *__restrict__ w)
+{
+    const int half = (n + 1) / 2;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // i-th largest root
+    if (i >= half) return;
+    double zr, wi;
+    gl_root(n, i, zr, wi);
     x[n - 1 - i] = zr;
     w[n - 1 - i] = wi;
     x[i] = -zr;
@@ -315,6 +328,25 @@ __global__ void k_bessel_chunk(int64_t nitems, const double *__restrict__ xs,
 }
 
 }  // namespace
+
+void gauss_legendre_host(int n, double *x, double *w)
+{
+    const int half = (n + 1) / 2;
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nth; ++t)
+        pool.emplace_back([=] {
+            for (int i = t; i < half; i += nth) {
+                double zr, wi;
+                gl_root(n, i, zr, wi);
+                x[n - 1 - i] = zr;
+                w[n - 1 - i] = wi;
+                x[i] = -zr;
+                w[i] = wi;
+            }
+        });
+    for (auto &th : pool) th.join();
+}
 
 hipError_t launch_gauss_legendre(int n, double *x, double *w, hipStream_t s)
 {

@@ -61,3 +61,52 @@ def test_create_without_device_reports_device_error(lib):
     st = lib.modal_create(ctypes.byref(h), 0, None)
     assert st == 4                                                   # MODAL_ERR_DEVICE
     assert h.value is None
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 97, 752, 3752])
+def test_host_gauss_legendre_vs_oracle(lib, n):
+    """modal_gauss_legendre without a context: the rule on the host (no
+    device), against the oracle's long-double Newton rule and exactly
+    symmetric.  The oracle's weights near +-1 carry the relative error
+    ~1e-19 / (1 - x^2) of its long-double 1 - x^2 (the mpmath test below pins
+    the library's to 1e-16 there)."""
+    import numpy as np
+    from oracle import oracle as O
+    x, w = np.empty(n), np.empty(n)
+    assert lib.modal_gauss_legendre(None, n, x.ctypes.data, w.ctypes.data) == 0
+    xr, wr = O.gauss_legendre(n)
+    assert np.abs(x - xr).max() <= 2.3e-16
+    one_minus = (1 - np.abs(xr)) * (1 + np.abs(xr))
+    assert np.all(np.abs(w - wr) / wr <= 1e-15 + 2e-19 / one_minus)
+    np.testing.assert_array_equal(x, -x[::-1])
+    np.testing.assert_array_equal(w, w[::-1])
+
+
+def test_host_gauss_legendre_end_nodes_vs_mpmath(lib):
+    """The host rule at n = 752, its largest nodes and a middle one, against
+    Newton's method at 40 digits."""
+    import numpy as np
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    n = 752
+    x, w = np.empty(n), np.empty(n)
+    assert lib.modal_gauss_legendre(None, n, x.ctypes.data, w.ctypes.data) == 0
+
+    def dP(t):
+        return n * (t * mpmath.legendre(n, t) - mpmath.legendre(n - 1, t)) / (t * t - 1)
+
+    for i in [n - 1, n - 2, n - 5, n // 2 + 3]:
+        root = mpmath.mpf(x[i])
+        for _ in range(4):
+            root -= mpmath.legendre(n, root) / dP(root)
+        wt = 2 / ((1 - root ** 2) * dP(root) ** 2)
+        assert abs(float(root) - x[i]) <= 1.2e-16
+        assert abs(float(wt) - w[i]) <= 2e-16 * float(wt)
+
+
+def test_host_gauss_legendre_errors(lib):
+    import numpy as np
+    x = np.empty(4)
+    assert lib.modal_gauss_legendre(None, 0, x.ctypes.data, x.ctypes.data) == 2          # SHAPE
+    assert lib.modal_gauss_legendre(None, 4, None, x.ctypes.data) == 1                   # INVALID_ARG
+    assert b"NULL" in lib.modal_last_error(None)

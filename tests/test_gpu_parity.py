@@ -67,6 +67,21 @@ def test_gauss_legendre(mp, ctx, oracle, n):
     np.testing.assert_array_equal(x, -x[::-1])
 
 
+@pytest.mark.parametrize("n", [97, 752, 3752, 6002])
+def test_gauss_legendre_host_equals_device(mp, ctx, n):
+    """The host rule (modal_gauss_legendre without a context) and the device
+    kernel run the same double-double refinement from slightly different
+    starting guesses (host and device cos): the same values to within one
+    unit in the last place (in practice the same bits)."""
+    x, w = (_np(v) for v in mp.gauss_legendre(ctx, n))
+    xh, wh = np.empty(n), np.empty(n)
+    assert mp.lib().modal_gauss_legendre(None, n, xh.ctypes.data, wh.ctypes.data) == 0
+    same = int((xh == x).sum() + (wh == w).sum())
+    print(f"GL n={n}: host and device rules agree bit for bit on {same} of {2 * n} values")
+    assert np.all(np.abs(xh - x) <= np.spacing(np.abs(x)))
+    assert np.all(np.abs(wh - w) <= np.spacing(w))
+
+
 def test_gauss_legendre_end_nodes_vs_mpmath(mp, ctx):
     mpmath = pytest.importorskip("mpmath")
     mpmath.mp.dps = 40
