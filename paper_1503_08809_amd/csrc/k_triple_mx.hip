@@ -23,17 +23,22 @@
 // outputs: a plain read-modify-write, no atomics, deterministic).  The mu
 // sum of an r is always complete before it enters the r sum (Sec. 2.2).
 //
-// Eight waves (two per SIMD): wave w owns rows 32 (w % 4) .. + 31 of the
-// task and pair tiles 8 (w / 4) .. + 7.  Per 32-wide z step a wave issues
-// 2 row blocks x 8 pair tiles x 3 products = 48 matrix-core operations, two
-// pair tiles at a time (12 operations ordered product by product, so that
-// dependent operations on one accumulator are four apart; 3 % faster than
-// one tile at a time, the same bits), reading the next two tiles from LDS
-// while the current two are multiplied; generates 2 of the 16 pair tiles for
-// the next step (its k rows read once for both) and shares them through LDS
-// (double-buffered, one barrier per step); loads its A fragments straight
-// from memory two steps ahead (two register sets); and all threads stage the
-// 32 source rows of the step after next.
+// Four waves per workgroup, two workgroups per CU (one wave of each per
+// SIMD, so that the barriers of the two fall at different times): wave w
+// owns rows 32 w .. + 31 of the task and all 16 pair tiles, so each A row
+// is loaded by one wave only.  Per 32-wide z step a wave issues 2 row
+// blocks x 16 pair tiles x 3 products = 96 matrix-core operations, two pair
+// tiles at a time (12 operations ordered product by product, so that
+// dependent operations on one accumulator are four apart), reading the next
+// two tiles from LDS while the current two are multiplied; generates 4 of
+// the 16 pair tiles for the next step (its k rows read once for all four)
+// and shares them through LDS (double-buffered, one barrier per step); loads
+// its A fragments straight from memory two steps ahead (two register sets);
+// and all threads stage the 32 source rows of the step after next, two rows
+// each.  A wave whose rows all exceed the task's largest j runs the same
+// steps (staging, generation, barriers) in a loop of its own without the
+// matrix-core work: a branch inside the step would make the compiler copy
+// the 128 accumulator registers and spill.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -48,7 +53,7 @@ typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 constexpr int BI = 128, BJ = 16, BK = 16;     // rows per task along i, j, k
 constexpr int RB = 2;                         // 16-row blocks per wave
-constexpr int TW = 8;                         // pair tiles per wave
+constexpr int TW = 16;                        // pair tiles per wave
 constexpr int NT = BJ;                        // pair tiles per task: (j, k0..k0+15)
 constexpr int KZ = 32;                        // z values per step
 constexpr int SRC_ROWS = BJ + BK;             // staged source rows per step
@@ -103,7 +108,7 @@ __device__ __host__ __forceinline__ int bt_offset(int il, int jl, int kl)
     return ((rb16 * NT + jl) * 64 + lane) * 4 + q;
 }
 
-__global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__restrict__ S32,
+__global__ __launch_bounds__(256, 2) void k_triple_bt(BTArgs A, const float *__restrict__ S32,
                                                    const uint16_t *__restrict__ SA,
                                                    double *__restrict__ T)
 {
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int rg = wave & 3, th = wave >> 2;   // row group (32 rows), tile half (8 tiles)
+    const int rg = wave;                       // row group (32 rows)
     const int task = task_of_block(blockIdx.x, A.ntasks);
     const int4 tk = A.tasks[task];
     const int i0 = tk.x * BI + rg * 16 * RB;   // this wave's rows
@@ -143,16 +148,24 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
         }
     };
     // source rows: local 0..15 = j0.., 16..31 = k0..; 32 rows x 16 float2,
-    // one per thread (every thread, so that no branch leaves the compiler
-    // unable to count this wave's outstanding loads)
+    // two per thread, rows srow and 16 + srow (every thread, so that no
+    // branch leaves the compiler unable to count this wave's outstanding
+    // loads)
     const int srow = t >> 4, sq = t & 15;
-    const uint32_t soff = ((uint32_t)(srow < BJ ? j0 + srow : k0 + srow - BJ) << 5) + 2 * sq;
+    const uint32_t soff0 = ((uint32_t)(j0 + srow) << 5) + 2 * sq;
+    const uint32_t soff1 = ((uint32_t)(k0 + srow) << 5) + 2 * sq;
     const size_t sstep = (size_t)A.upad << 5;
-    float2 sreg = make_float2(0.f, 0.f);
-    auto sload = [&](int64_t s) { sreg = *reinterpret_cast<const float2 *>(S32 + (size_t)s * sstep + soff); };
-    auto sstore = [&](int buf) { *reinterpret_cast<float2 *>(&Src[buf][srow][2 * sq]) = sreg; };
-    // this wave generates pair tiles 2 wave and 2 wave + 1 (tile = j local);
-    // the k values (this lane's k row, 8 z) are read once for both
+    float2 sreg0 = make_float2(0.f, 0.f), sreg1 = sreg0;
+    auto sload = [&](int64_t s) {
+        sreg0 = *reinterpret_cast<const float2 *>(S32 + (size_t)s * sstep + soff0);
+        sreg1 = *reinterpret_cast<const float2 *>(S32 + (size_t)s * sstep + soff1);
+    };
+    auto sstore = [&](int buf) {
+        *reinterpret_cast<float2 *>(&Src[buf][srow][2 * sq]) = sreg0;
+        *reinterpret_cast<float2 *>(&Src[buf][BJ + srow][2 * sq]) = sreg1;
+    };
+    // this wave generates pair tiles 4 wave .. + 3 (tile = j local); the k
+    // values (this lane's k row, 8 z) are read once for all four
     f4 k0v, k1v;
     auto bgen_k = [&](int buf) {
         const float *pk = &Src[buf][BJ + n][8 * zg];
@@ -160,7 +173,7 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
         k1v = *reinterpret_cast<const f4 *>(pk + 4);
     };
     auto bgen_tile = [&](int buf, int q) {
-        const int tile = 2 * wave + q;
+        const int tile = 4 * wave + q;
         const float *pj = &Src[buf][tile][8 * zg];
         const f4 j0v = *reinterpret_cast<const f4 *>(pj), j1v = *reinterpret_cast<const f4 *>(pj + 4);
         float v[8];
@@ -176,9 +189,9 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
         Bb[buf][tile][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
     };
 
-    // this wave's output: tile jl = TW th + j of row block rb16 = RB rg + i at
+    // this wave's output: tile jl = j of row block rb16 = RB rg + i at
     // T + task * TASK_SIZE + ((rb16 * NT + jl) * 64 + lane) * 4
-    double *tbase = T + (size_t)task * TASK_SIZE + (size_t)(rg * RB * NT + th * TW) * 256;
+    double *tbase = T + (size_t)task * TASK_SIZE + (size_t)(rg * RB * NT) * 256;
     const uint32_t toff = (uint32_t)lane * 4;
 
     const int64_t nsteps = A.nsteps, last = nsteps - 1;
@@ -190,6 +203,8 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
     bgen_k(0);
     bgen_tile(0, 0);
     bgen_tile(0, 1);
+    bgen_tile(0, 2);
+    bgen_tile(0, 3);
     sload(nsteps > 2 ? 2 : last);
     aload(0, ah0, al0);
     aload(nsteps > 1 ? 1 : 0, ah1, al1);
@@ -198,35 +213,37 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
     int kin = 0;
     bool first = true;
     int64_t s = 0;
-    // one step with parity P (LDS buffers and A set P); false when done
-    auto step = [&](auto par) -> bool {
+    // one step with parity P (LDS buffers and A set P), with or without the
+    // matrix-core work; false when done
+    auto step = [&](auto par, auto act) -> bool {
         constexpr int P = decltype(par)::value;
+        constexpr bool work = decltype(act)::value;
         constexpr int buf = P;
         uint4(&ah)[RB] = P ? ah1 : ah0;
         uint4(&al)[RB] = P ? al1 : al0;
         // past the last step these clamp to it; their results are never used
         sstore(buf);                                       // sources of step s + 2
         sload(s + 3 < last ? s + 3 : last);
-        if (active) {
+        if constexpr (work) {
             // pairs of pair tiles: the operands of pair p + 1 are read while
             // pair p's 12 matrix-core operations run, ordered product by
             // product over both tiles and both row blocks so that dependent
-            // operations on one accumulator are four apart; this wave's 2
-            // pair tiles of step s + 1 are generated after pairs 1 and 3
-            // (VALU work under the matrix cores)
+            // operations on one accumulator are four apart; this wave's 4
+            // pair tiles of step s + 1 are generated after pairs 1, 3, 5 and
+            // 7 (VALU work under the matrix cores)
             uint4 ch[2], cl[2], nh[2], nl[2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                ch[q] = Bb[buf][th * TW + q][0][lane];
-                cl[q] = Bb[buf][th * TW + q][1][lane];
+                ch[q] = Bb[buf][q][0][lane];
+                cl[q] = Bb[buf][q][1][lane];
             }
 #pragma unroll
             for (int p = 0; p < TW / 2; ++p) {
                 if (p + 1 < TW / 2) {
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        nh[q] = Bb[buf][th * TW + 2 * p + 2 + q][0][lane];
-                        nl[q] = Bb[buf][th * TW + 2 * p + 2 + q][1][lane];
+                        nh[q] = Bb[buf][2 * p + 2 + q][0][lane];
+                        nl[q] = Bb[buf][2 * p + 2 + q][1][lane];
                     }
                 }
 #pragma unroll
@@ -257,12 +274,14 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
             bgen_k(buf ^ 1);
             bgen_tile(buf ^ 1, 0);
             bgen_tile(buf ^ 1, 1);
+            bgen_tile(buf ^ 1, 2);
+            bgen_tile(buf ^ 1, 3);
         }
         if (++kin == A.kpr) {
             // this r's mu sum is complete: add it to the FP64 r sum in T,
             // four tiles at a time with their loads issued first
             kin = 0;
-            if (active) {
+            if constexpr (work) {
                 // opaque copy: keeps the compiler from hoisting every tile
                 // address out of the z loop
                 uint32_t to = toff;
@@ -299,9 +318,16 @@ __global__ __launch_bounds__(512) void k_triple_bt(BTArgs A, const float *__rest
         lds_barrier();
         return ++s < nsteps;
     };
-    for (;;) {
-        if (!step(std::integral_constant<int, 0>())) break;
-        if (!step(std::integral_constant<int, 1>())) break;
+    if (active) {
+        for (;;) {
+            if (!step(std::integral_constant<int, 0>(), std::true_type())) break;
+            if (!step(std::integral_constant<int, 1>(), std::true_type())) break;
+        }
+    } else {
+        for (;;) {
+            if (!step(std::integral_constant<int, 0>(), std::false_type())) break;
+            if (!step(std::integral_constant<int, 1>(), std::false_type())) break;
+        }
     }
 }
 
@@ -400,7 +426,7 @@ hipError_t launch_triple_bt(const BTPlan &plan, int64_t upad, int64_t ldz, int n
     a.upad = upad;
     a.nsteps = ldz / KZ;
     a.kpr = nmu_pad / KZ;
-    hipLaunchKernelGGL(k_triple_bt, dim3(plan.ntasks), dim3(512), 0, s, a, S32, SA, T);
+    hipLaunchKernelGGL(k_triple_bt, dim3(plan.ntasks), dim3(256), 0, s, a, S32, SA, T);
     return hipGetLastError();
 }
 
