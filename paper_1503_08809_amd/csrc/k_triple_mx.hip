@@ -10,35 +10,38 @@
 // every task of the same ib; tasks are ordered (ib, jb, kb) and dealt to
 // the XCDs in contiguous runs so that co-resident workgroups read the same A
 // rows through one L2.  Only tasks holding some i <= j <= k are launched;
-// inside one, waves whose 32 rows all exceed the largest j skip the matrix
-// work, and the remaining out-of-order entries are computed but never read.
+// inside one, only the row blocks holding some i <= j (rounded up to an
+// even count) are multiplied, and the remaining out-of-order entries are
+// computed but never read.
 //
 // Arithmetic: each value x is split as x = hi + lo with hi the BF16 rounding
 // of x and lo the BF16 rounding of the remainder; a term A B is formed by
 // v_mfma_f32_16x16x32_bf16 as A_lo B_hi + A_hi B_lo + A_hi B_hi (the dropped
 // A_lo B_lo is ~2^-16 of the term).  The A rows are split once in memory;
-// the product operand St_j St_k is formed in FP32 and split per step.  Each
-// r's mu sum accumulates in FP32 in the matrix-core accumulators; when it
-// is complete it is added to the FP64 r sum held in T (each task owns its
+// the product operand St_j St_k is formed in FP32 and split per step, its
+// remainder taken from the exact product by a fused multiply-add.  Each r's
+// mu sum accumulates in FP32 in the matrix-core accumulators; when it is
+// complete it is added to the FP64 r sum held in T (each task owns its
 // outputs: a plain read-modify-write, no atomics, deterministic).  The mu
 // sum of an r is always complete before it enters the r sum (Sec. 2.2).
 //
 // Four waves per workgroup, two workgroups per CU (one wave of each per
-// SIMD, so that the barriers of the two fall at different times): wave w
-// owns rows 32 w .. + 31 of the task and all 16 pair tiles, so each A row
-// is loaded by one wave only.  Per 32-wide z step a wave issues 2 row
-// blocks x 16 pair tiles x 3 products = 96 matrix-core operations, two pair
-// tiles at a time (12 operations ordered product by product, so that
-// dependent operations on one accumulator are four apart), reading the next
-// two tiles from LDS while the current two are multiplied; generates 4 of
-// the 16 pair tiles for the next step (its k rows read once for all four)
-// and shares them through LDS (double-buffered, one barrier per step); loads
-// its A fragments straight from memory two steps ahead (two register sets);
-// and all threads stage the 32 source rows of the step after next, two rows
-// each.  A wave whose rows all exceed the task's largest j runs the same
-// steps (staging, generation, barriers) in a loop of its own without the
-// matrix-core work: a branch inside the step would make the compiler copy
-// the 128 accumulator registers and spill.
+// SIMD, so that the barriers of the two fall at different times).  Wave w
+// owns the 4 pair tiles j = 4 w .. + 3 (k = the 16 k of the task) for all
+// 128 rows, and generates exactly those tiles itself, straight into the
+// registers that the matrix cores take as B operands: no pair tile passes
+// through LDS.  The A fragments of a step (the task's 128 rows, split, 16 KB)
+// are copied from memory straight into LDS (buffer_load ... lds, four
+// instructions per wave) one step ahead into the other of two buffers, and
+// every wave reads all 8 row blocks of them.  Per 32-wide z step a wave
+// issues up to 8 row blocks x 4 pair tiles x 3 products = 96 matrix-core
+// operations, row block by row block (12 operations ordered product by
+// product over the four tiles, so that dependent operations on one
+// accumulator are four apart), reading the next block's fragments while the
+// current one is multiplied; then generates its tiles of the next step from
+// the staged source rows (double-buffered in LDS, two rows per thread,
+// loaded three steps ahead); one barrier per step.  Against 32 rows x 16
+// shared pair tiles per wave this halves the LDS operand reads per step.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -52,28 +55,22 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 constexpr int BI = 128, BJ = 16, BK = 16;     // rows per task along i, j, k
-constexpr int RB = 2;                         // 16-row blocks per wave
-constexpr int TW = 16;                        // pair tiles per wave
 constexpr int NT = BJ;                        // pair tiles per task: (j, k0..k0+15)
 constexpr int KZ = 32;                        // z values per step
 constexpr int SRC_ROWS = BJ + BK;             // staged source rows per step
 constexpr int SRC_LD = KZ + 4;                // padded LDS row (floats)
 constexpr int TASK_SIZE = BI * BJ * BK;       // moments per task
 
-__device__ __forceinline__ void lds_barrier()
+// The products p = x y, q = u w split as p = hi + lo: hi the BF16 rounding of
+// the FP32 product, lo the BF16 rounding of the exact remainder x y - hi
+// (one fused multiply-add, so the product's own rounding error is kept).
+__device__ __forceinline__ void split_prod2(float x, float y, float u, float w, uint32_t &h, uint32_t &l)
 {
-    __builtin_amdgcn_s_waitcnt(0xc07f);       // lgkmcnt(0) only: global loads stay in flight
-    __builtin_amdgcn_s_barrier();
-}
-
-// x = hi + lo for two values a, b: hi and lo are BF16 roundings to nearest
-// even (v_cvt_pk_bf16_f32), packed as (a, b) halves of h and l.
-__device__ __forceinline__ void split2(float a, float b, uint32_t &h, uint32_t &l)
-{
-    const bf2 hv = {(__bf16)a, (__bf16)b};
+    const bf2 hv = {(__bf16)(x * y), (__bf16)(u * w)};
     h = __builtin_bit_cast(uint32_t, hv);
     asm("" : "+v"(h));                        // keep one conversion: unpack h itself below
-    const bf2 lv = {(__bf16)(a - __uint_as_float(h << 16)), (__bf16)(b - __uint_as_float(h & 0xffff0000u))};
+    const bf2 lv = {(__bf16)__builtin_fmaf(x, y, -__uint_as_float(h << 16)),
+                    (__bf16)__builtin_fmaf(u, w, -__uint_as_float(h & 0xffff0000u))};
     l = __builtin_bit_cast(uint32_t, lv);
 }
 
@@ -108,49 +105,58 @@ __device__ __host__ __forceinline__ int bt_offset(int il, int jl, int kl)
     return ((rb16 * NT + jl) * 64 + lane) * 4 + q;
 }
 
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, uint4 *lds_base)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)lds_base, 16, voff, soff,
+                                             0, 0);
+}
+constexpr int kBufWord3 = 0x00020000;         // descriptor word 3: 32-bit data format, raw access
+constexpr int NRB = BI / 16;                  // row blocks per task
+constexpr int TQ = 4;                         // pair tiles per wave
+constexpr int ASLOT = NRB * 128;              // uint4 per A buffer: [row block][hi/lo][lane]
+
 __global__ __launch_bounds__(256, 2) void k_triple_bt(BTArgs A, const float *__restrict__ S32,
                                                    const uint16_t *__restrict__ SA,
                                                    double *__restrict__ T)
 {
     __shared__ float Src[2][SRC_ROWS][SRC_LD];
-    __shared__ uint4 Bb[2][NT][2][64];        // [buf][tile][hi/lo][lane]
+    __shared__ uint4 abuf0[ASLOT], abuf1[ASLOT];
 
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int rg = wave;                       // row group (32 rows)
     const int task = task_of_block(blockIdx.x, A.ntasks);
     const int4 tk = A.tasks[task];
-    const int i0 = tk.x * BI + rg * 16 * RB;   // this wave's rows
     const int j0 = tk.y * BJ, k0 = tk.z * BK;
     const int n = lane & 15, zg = lane >> 4;
-    const bool active = i0 <= j0 + BJ - 1;     // some row <= some j (wave-uniform)
+    // row blocks holding some i <= j0 + BJ - 1 (at least one: tasks are
+    // launched only then), rounded up to even
+    const int live = min(NRB, (j0 + BJ - 1 - tk.x * BI) / 16 + 1);
+    const int nl = min(NRB, (live + 1) & ~1);
 
-    f4 acc[RB][TW];
+    f4 acc[NRB][TQ];
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
+    for (int i = 0; i < NRB; ++i)
 #pragma unroll
-        for (int j = 0; j < TW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TQ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // A fragments of step s: row i0 + 16 i + n, 8-z group zg, at
-    // SA[((s * upad + row) * 4 + zg) * 16]; 32-bit lane offsets from a
-    // wave-uniform base keep the addressing in scalar registers plus one VGPR
-    const uint32_t aoff = ((uint32_t)(i0 + n) * 4 + zg) << 4;     // uint16 units
-    const size_t astep = (size_t)A.upad << 6;
-    // two sets: step s uses set s % 2, whose loads were issued two steps ahead
-    uint4 ah0[RB], al0[RB], ah1[RB], al1[RB];
-    auto aload = [&](int64_t s, uint4 (&ah)[RB], uint4 (&al)[RB]) {
-        const uint16_t *base = SA + (size_t)s * astep;
+    // A fragments of step s (the task's 128 rows, split, 16 KB) copied into
+    // LDS: this wave copies row blocks 2 wave, 2 wave + 1, hi and lo each;
+    // lane (n, zg) takes row 16 rb + n, 8-z group zg at byte
+    // ((row * 4 + zg) * 32) (hi) and + 16 (lo) of the task's rows
+    const size_t astep = (size_t)A.upad << 6;                     // uint16 per step
+    const uint32_t avoff = (uint32_t)(n * 4 + zg) * 32;
+    auto acopy = [&](int64_t s, uint4 *buf) {
+        const uint16_t *base = SA + (size_t)s * astep + (size_t)tk.x * BI * 64;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, BI * 128, kBufWord3);
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(base + aoff + (uint32_t)(i * 16 * 64));
-            ah[i] = p[0];
-            al[i] = p[1];
+        for (int h = 0; h < 2; ++h) {
+            const int rb = 2 * wave + h;
+            dma16(rs, avoff, rb * 2048, buf + (rb * 2) * 64);
+            dma16(rs, avoff, rb * 2048 + 16, buf + (rb * 2 + 1) * 64);
         }
     };
     // source rows: local 0..15 = j0.., 16..31 = k0..; 32 rows x 16 float2,
-    // two per thread, rows srow and 16 + srow (every thread, so that no
-    // branch leaves the compiler unable to count this wave's outstanding
-    // loads)
+    // two per thread, rows srow and 16 + srow
     const int srow = t >> 4, sq = t & 15;
     const uint32_t soff0 = ((uint32_t)(j0 + srow) << 5) + 2 * sq;
     const uint32_t soff1 = ((uint32_t)(k0 + srow) << 5) + 2 * sq;
@@ -164,34 +170,35 @@ __global__ __launch_bounds__(256, 2) void k_triple_bt(BTArgs A, const float *__r
         *reinterpret_cast<float2 *>(&Src[buf][srow][2 * sq]) = sreg0;
         *reinterpret_cast<float2 *>(&Src[buf][BJ + srow][2 * sq]) = sreg1;
     };
-    // this wave generates pair tiles 4 wave .. + 3 (tile = j local); the k
-    // values (this lane's k row, 8 z) are read once for all four
-    f4 k0v, k1v;
-    auto bgen_k = [&](int buf) {
+    // this wave's pair tiles j = 4 wave + q (q < 4), k = k0 + n: generated in
+    // registers as the matrix-core B operands (hi, lo)
+    uint4 bh[TQ], bl[TQ];
+    auto bgen = [&](int buf) {
         const float *pk = &Src[buf][BJ + n][8 * zg];
-        k0v = *reinterpret_cast<const f4 *>(pk);
-        k1v = *reinterpret_cast<const f4 *>(pk + 4);
-    };
-    auto bgen_tile = [&](int buf, int q) {
-        const int tile = 4 * wave + q;
-        const float *pj = &Src[buf][tile][8 * zg];
-        const f4 j0v = *reinterpret_cast<const f4 *>(pj), j1v = *reinterpret_cast<const f4 *>(pj + 4);
-        float v[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            v[e] = j0v[e] * k0v[e];
-            v[4 + e] = j1v[e] * k1v[e];
+        for (int q = 0; q < TQ; ++q) {
+            const f4 k0v = *reinterpret_cast<const f4 *>(pk), k1v = *reinterpret_cast<const f4 *>(pk + 4);
+            const float *pj = &Src[buf][4 * wave + q][8 * zg];
+            const f4 j0v = *reinterpret_cast<const f4 *>(pj), j1v = *reinterpret_cast<const f4 *>(pj + 4);
+            float jv[8], kv[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                jv[e] = j0v[e];
+                jv[4 + e] = j1v[e];
+                kv[e] = k0v[e];
+                kv[4 + e] = k1v[e];
+            }
+            uint32_t h[4], l[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) split_prod2(jv[2 * e], kv[2 * e], jv[2 * e + 1], kv[2 * e + 1], h[e], l[e]);
+            bh[q] = make_uint4(h[0], h[1], h[2], h[3]);
+            bl[q] = make_uint4(l[0], l[1], l[2], l[3]);
         }
-        uint32_t h[4], l[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) split2(v[2 * e], v[2 * e + 1], h[e], l[e]);
-        Bb[buf][tile][0][lane] = make_uint4(h[0], h[1], h[2], h[3]);
-        Bb[buf][tile][1][lane] = make_uint4(l[0], l[1], l[2], l[3]);
     };
 
-    // this wave's output: tile jl = j of row block rb16 = RB rg + i at
-    // T + task * TASK_SIZE + ((rb16 * NT + jl) * 64 + lane) * 4
-    double *tbase = T + (size_t)task * TASK_SIZE + (size_t)(rg * RB * NT) * 256;
+    // output tile (row block rb, pair tile 4 wave + q) at
+    // T + task * TASK_SIZE + ((rb * NT + 4 wave + q) * 64 + lane) * 4
+    double *tbase = T + (size_t)task * TASK_SIZE + (size_t)(4 * wave) * 256;
     const uint32_t toff = (uint32_t)lane * 4;
 
     const int64_t nsteps = A.nsteps, last = nsteps - 1;
@@ -199,136 +206,101 @@ __global__ __launch_bounds__(256, 2) void k_triple_bt(BTArgs A, const float *__r
     sstore(0);
     sload(nsteps > 1 ? 1 : 0);
     sstore(1);
-    lds_barrier();
-    bgen_k(0);
-    bgen_tile(0, 0);
-    bgen_tile(0, 1);
-    bgen_tile(0, 2);
-    bgen_tile(0, 3);
+    acopy(0, abuf0);
+    __builtin_amdgcn_s_waitcnt(0xc07f);                                 // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    bgen(0);
     sload(nsteps > 2 ? 2 : last);
-    aload(0, ah0, al0);
-    aload(nsteps > 1 ? 1 : 0, ah1, al1);
-    lds_barrier();
 
     int kin = 0;
     bool first = true;
     int64_t s = 0;
-    // one step with parity P (LDS buffers and A set P), with or without the
-    // matrix-core work; false when done
-    auto step = [&](auto par, auto act) -> bool {
+    // one step with parity P (A buffer P, sources of step s + 1 in Src[1 - P])
+    // over NL row blocks; false when done
+    auto step = [&](auto par, auto rows) -> bool {
         constexpr int P = decltype(par)::value;
-        constexpr bool work = decltype(act)::value;
-        constexpr int buf = P;
-        uint4(&ah)[RB] = P ? ah1 : ah0;
-        uint4(&al)[RB] = P ? al1 : al0;
-        // past the last step these clamp to it; their results are never used
-        sstore(buf);                                       // sources of step s + 2
+        constexpr int NL = decltype(rows)::value;
+        const uint4 *ab = P ? abuf1 : abuf0;
+        uint4 *abn = P ? abuf0 : abuf1;
+        // this step's A copies and every wave's source stores are complete
+        __builtin_amdgcn_s_waitcnt(0x0070);                             // vmcnt(0) lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        sstore(P);                                                      // sources of step s + 2
         sload(s + 3 < last ? s + 3 : last);
-        if constexpr (work) {
-            // pairs of pair tiles: the operands of pair p + 1 are read while
-            // pair p's 12 matrix-core operations run, ordered product by
-            // product over both tiles and both row blocks so that dependent
-            // operations on one accumulator are four apart; this wave's 4
-            // pair tiles of step s + 1 are generated after pairs 1, 3, 5 and
-            // 7 (VALU work under the matrix cores)
-            uint4 ch[2], cl[2], nh[2], nl[2];
+        acopy(s + 1 < last ? s + 1 : last, abn);                        // A of step s + 1
+        // row block by row block, the next block's fragments read while this
+        // one's 12 matrix-core operations run (product by product over the
+        // four tiles, so that dependent operations are four apart)
+        uint4 ah = ab[lane], al = ab[64 + lane];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                ch[q] = Bb[buf][q][0][lane];
-                cl[q] = Bb[buf][q][1][lane];
+        for (int rb = 0; rb < NL; ++rb) {
+            uint4 nh, nl2;
+            if (rb + 1 < NL) {
+                nh = ab[((rb + 1) * 2) * 64 + lane];
+                nl2 = ab[((rb + 1) * 2 + 1) * 64 + lane];
             }
 #pragma unroll
-            for (int p = 0; p < TW / 2; ++p) {
-                if (p + 1 < TW / 2) {
+            for (int q = 0; q < TQ; ++q)
+                acc[rb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al), as_bf8(bh[q]), acc[rb][q], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < TQ; ++q)
+                acc[rb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah), as_bf8(bl[q]), acc[rb][q], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < TQ; ++q)
+                acc[rb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah), as_bf8(bh[q]), acc[rb][q], 0, 0, 0);
+            if (rb + 1 < NL) {
+                ah = nh;
+                al = nl2;
+            }
+        }
+        bgen(1 - P);                                                    // operands of step s + 1
+        if (++kin == A.kpr) {
+            // this r's mu sum is complete: add it to the FP64 r sum in T
+            kin = 0;
+            uint32_t to = toff;
+            asm volatile("" : "+v"(to));
+#pragma unroll
+            for (int rb = 0; rb < NL; ++rb)
+#pragma unroll
+                for (int qh = 0; qh < TQ; qh += 2) {
+                    double2 old[2][2];
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        nh[q] = Bb[buf][2 * p + 2 + q][0][lane];
-                        nl[q] = Bb[buf][2 * p + 2 + q][1][lane];
+                        const double2 *p =
+                            reinterpret_cast<const double2 *>(tbase + to + (uint32_t)((rb * NT + qh + q) << 8));
+                        old[q][0] = first ? make_double2(0.0, 0.0) : p[0];
+                        old[q][1] = first ? make_double2(0.0, 0.0) : p[1];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        double2 *p = reinterpret_cast<double2 *>(tbase + to + (uint32_t)((rb * NT + qh + q) << 8));
+                        const f4 a = acc[rb][qh + q];
+                        p[0] = make_double2(old[q][0].x + (double)a[0], old[q][0].y + (double)a[1]);
+                        p[1] = make_double2(old[q][1].x + (double)a[2], old[q][1].y + (double)a[3]);
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q)
+            for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-                    for (int i = 0; i < RB; ++i)
-                        acc[i][2 * p + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(al[i]), as_bf8(ch[q]), acc[i][2 * p + q], 0, 0, 0);
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int i = 0; i < RB; ++i)
-                        acc[i][2 * p + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), as_bf8(cl[q]), acc[i][2 * p + q], 0, 0, 0);
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int i = 0; i < RB; ++i)
-                        acc[i][2 * p + q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ah[i]), as_bf8(ch[q]), acc[i][2 * p + q], 0, 0, 0);
-                if (p == 1) bgen_k(buf ^ 1);
-                if ((p & 1) == 1) bgen_tile(buf ^ 1, p >> 1);      // operand of step s + 1
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    ch[q] = nh[q];
-                    cl[q] = nl[q];
-                }
-            }
-        } else {
-            bgen_k(buf ^ 1);
-            bgen_tile(buf ^ 1, 0);
-            bgen_tile(buf ^ 1, 1);
-            bgen_tile(buf ^ 1, 2);
-            bgen_tile(buf ^ 1, 3);
-        }
-        if (++kin == A.kpr) {
-            // this r's mu sum is complete: add it to the FP64 r sum in T,
-            // four tiles at a time with their loads issued first
-            kin = 0;
-            if constexpr (work) {
-                // opaque copy: keeps the compiler from hoisting every tile
-                // address out of the z loop
-                uint32_t to = toff;
-                asm volatile("" : "+v"(to));
-#pragma unroll
-                for (int i = 0; i < RB; ++i)
-#pragma unroll
-                    for (int jh = 0; jh < TW; jh += 4) {
-                        double2 old[4][2];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const double2 *p = reinterpret_cast<const double2 *>(
-                                tbase + to + (uint32_t)((i * NT + jh + j) << 8));
-                            old[j][0] = first ? make_double2(0.0, 0.0) : p[0];
-                            old[j][1] = first ? make_double2(0.0, 0.0) : p[1];
-                        }
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            double2 *p = reinterpret_cast<double2 *>(tbase + to + (uint32_t)((i * NT + jh + j) << 8));
-                            const f4 a = acc[i][jh + j];
-                            p[0] = make_double2(old[j][0].x + (double)a[0], old[j][0].y + (double)a[1]);
-                            p[1] = make_double2(old[j][1].x + (double)a[2], old[j][1].y + (double)a[3]);
-                        }
-                    }
-            }
-#pragma unroll
-            for (int i = 0; i < RB; ++i)
-#pragma unroll
-                for (int j = 0; j < TW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+                for (int q = 0; q < TQ; ++q) acc[rb][q] = f4{0.f, 0.f, 0.f, 0.f};
             first = false;
         }
-        // A fragments of step s + 2 into the set this step has finished with
-        aload(s + 2 < last ? s + 2 : last, ah, al);
-        lds_barrier();
         return ++s < nsteps;
     };
-    if (active) {
+    auto run = [&](auto rows) {
         for (;;) {
-            if (!step(std::integral_constant<int, 0>(), std::true_type())) break;
-            if (!step(std::integral_constant<int, 1>(), std::true_type())) break;
+            if (!step(std::integral_constant<int, 0>(), rows)) break;
+            if (!step(std::integral_constant<int, 1>(), rows)) break;
         }
-    } else {
-        for (;;) {
-            if (!step(std::integral_constant<int, 0>(), std::false_type())) break;
-            if (!step(std::integral_constant<int, 1>(), std::false_type())) break;
-        }
+    };
+    switch (nl) {
+    case 2: run(std::integral_constant<int, 2>()); break;
+    case 4: run(std::integral_constant<int, 4>()); break;
+    case 6: run(std::integral_constant<int, 6>()); break;
+    default: run(std::integral_constant<int, 8>()); break;
     }
+    // no copy into this workgroup's LDS may outlive it
+    __builtin_amdgcn_s_waitcnt(0x0f70);                                 // vmcnt(0)
 }
 
 // ---- gather ---------------------------------------------------------------
