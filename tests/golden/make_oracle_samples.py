@@ -20,6 +20,7 @@ highest (N1-1, N1-1, N1-1); for the ordered lists the distinct low triple
 is (2, 1, 0), whose order differs from the sorted one.
 
     python tests/golden/make_oracle_samples.py [workload name ...]
+    python tests/golden/make_oracle_samples.py grad     (the lmax = 1000 gradient)
 """
 import gzip
 import os
@@ -85,5 +86,44 @@ def main(names):
         print(f"wrote {path_for(name)} ({rows.size} entries, {time.time() - t0:.0f} s)", flush=True)
 
 
+# ---- the gradient at lmax = 1000 ------------------------------------------
+# The loss of the forward + adjoint workload, L = Sum (Gamma * W)^2 with W the
+# seeded N(0,1) matrix of synth.loss_weights: the oracle's full Gamma, then
+# its adjoint for dL/dGamma = 2 Gamma W^2.  Stored: all of dL/dq [np][nk] and
+# the rows dL/dDelta_l(k) for l in GRAD_L (every k), "kind index k value".
+GRAD_WORKLOAD = "lmax1000_symmetric_n20"
+GRAD_L = [2, 3, 4, 10, 50, 100, 200, 333, 500, 501, 640, 777, 900, 950, 990, 998, 999, 1000]
+
+
+def grad_path(name: str) -> str:
+    return os.path.join(HERE, f"oracle_grad_{name}.txt.gz")
+
+
+def main_grad(name: str = GRAD_WORKLOAD):
+    t0 = time.time()
+    cfg = synth.workload(name)
+    inp = synth.make_inputs(cfg)
+    g = O.gamma_full(inp)
+    print(f"oracle Gamma {g.shape} in {time.time() - t0:.0f} s", flush=True)
+    W = synth.loss_weights(cfg, g.shape[0], g.shape[1])
+    dq, dd = O.gamma_full_backward(inp, 2.0 * g * W * W)
+    with gzip.open(grad_path(name), "wt") as f:
+        f.write(f"# oracle gradient of L = Sum (Gamma * W)^2 (W = synth.loss_weights), workload {cfg.name}\n")
+        f.write(f"# all of dL/dq [{dq.shape[0]}][{dq.shape[1]}] ('q p k value'), and dL/dDelta_l(k) for l in "
+                f"{GRAD_L} ('d l k value'); L = {float(((g * W) ** 2).sum()):.17g}\n")
+        f.write("# written by tests/golden/make_oracle_samples.py from the oracle only\n")
+        for p in range(dq.shape[0]):
+            for k in range(dq.shape[1]):
+                f.write(f"q {p} {k} {dq[p, k]:.17g}\n")
+        for l in GRAD_L:
+            for k in range(dd.shape[1]):
+                f.write(f"d {l} {k} {dd[l - cfg.lmin, k]:.17g}\n")
+    print(f"wrote {grad_path(name)} in {time.time() - t0:.0f} s", flush=True)
+
+
 if __name__ == "__main__":
-    main(sys.argv[1:] or WORKLOADS)
+    args = sys.argv[1:]
+    if args == ["grad"]:
+        main_grad()
+    else:
+        main(args or WORKLOADS)

@@ -11,6 +11,7 @@ entries that cancel to almost nothing and for the largest ones alike.
 """
 import gzip
 import os
+import re
 
 import numpy as np
 
@@ -47,3 +48,24 @@ def check(g, name: str, tol: float, label: str = "") -> float:
     print(f"{label or name}: {rows.size} stored entries, worst |G - ref| / scale = {w:.2e}")
     assert w <= tol, (label or name, w)
     return w
+
+
+def load_grad(name: str):
+    """The stored oracle gradient of L = Sum (Gamma * W)^2 at a workload:
+    (dL/dq [np][nk] in full, {l: dL/dDelta_l(k) row}, L), written by
+    tests/golden/make_oracle_samples.py grad."""
+    p = os.path.join(GOLDEN, f"oracle_grad_{name}.txt.gz")
+    q, d, L = {}, {}, None
+    with gzip.open(p, "rt") as f:
+        for line in f:
+            if line.startswith("#"):
+                m = re.search(r"; L = ([-+0-9.eE]+)", line)
+                if m:
+                    L = float(m.group(1))
+                continue
+            kind, i, k, v = line.split()
+            (q if kind == "q" else d).setdefault(int(i), {})[int(k)] = float(v)
+    nq, nk = max(q) + 1, max(q[0]) + 1
+    dq = np.array([[q[i][k] for k in range(nk)] for i in range(nq)])
+    rows = {l: np.array([d[l][k] for k in range(nk)]) for l in sorted(d)}
+    return dq, rows, L

@@ -290,6 +290,35 @@ def test_lmax1000_finite_differences_and_mixed(mp, ctx):
     assert eq <= 1e-4 and ed <= 1e-4
 
 
+def test_lmax1000_gradient_vs_stored_oracle(mp, ctx):
+    """lmax = 1000, L = Sum (Gamma * W)^2: the gradient against the oracle's
+    (stored: all of dL/dq, and dL/dDelta_l(k) at 18 values of l, every k),
+    elementwise.  FP64: within 1e-10 of the largest stored value of each
+    gradient, and 1e-8 relative on the entries above 1e-3 of it; mixed: the
+    1e-4 bar."""
+    import stored_rows
+    cfg = synth.workload("lmax1000_symmetric_n20")
+    rq, rows, _ = stored_rows.load_grad(cfg.name)
+    ls = sorted(rows)
+    rd = np.stack([rows[l] for l in ls])
+    inp = synth.make_inputs(cfg)
+    pr = mp.projection_from_inputs(ctx, inp)
+    W = ctx.to_dev(synth.loss_weights(cfg, inp.tri_a.shape[0], inp.tri_p.shape[0]))
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-4)):
+        G = pr.gamma(prec)
+        dq, dd = pr.gamma_backward(2 * G * W * W, prec)
+        dq, dd = _np(dq), _np(dd)[[l - cfg.lmin for l in ls]]
+        eq, ed = normwise(dq, rq), normwise(dd, rd)
+        big_q, big_d = np.abs(rq) >= 1e-3 * np.abs(rq).max(), np.abs(rd) >= 1e-3 * np.abs(rd).max()
+        rel_q = float((np.abs(dq - rq)[big_q] / np.abs(rq[big_q])).max())
+        rel_d = float((np.abs(dd - rd)[big_d] / np.abs(rd[big_d])).max())
+        print(f"{prec} gradient vs stored oracle at lmax=1000: dq {eq:.2e} ({rq.size} entries, large "
+              f"ones {rel_q:.2e} relative), ddelta {ed:.2e} ({rd.size} entries, {rel_d:.2e})")
+        assert eq <= tol and ed <= tol
+        if prec == "fp64":
+            assert rel_q <= 1e-8 and rel_d <= 1e-8
+
+
 def test_lmax2500_gradient_full_size(mp, ctx):
     """lmax = 2500, 4960 x 4960 symmetric Gamma, L = Sum (Gamma * W)^2.
 

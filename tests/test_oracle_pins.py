@@ -479,3 +479,17 @@ def test_stored_rows_detect_a_perturbed_S_row(oracle):
         Sp[k] *= factor
         gp = oracle.gamma_from_S(inp, wmu, Sp, sidx)
         assert stored_rows.worst(gp, ref[sel], scale[sel]) > bar, factor
+
+
+def test_stored_gradient_satisfies_euler_identity():
+    """The stored oracle gradient at lmax = 1000 (GPU parity of the adjoint
+    reads it): Gamma is cubic in q (beta is linear in q), so
+    L = Sum (Gamma * W)^2 is homogeneous of degree 6 in q and
+    <dL/dq, q> = 6 L exactly; L is the oracle's, stored with the gradient."""
+    import stored_rows
+    cfg = synth.workload("lmax1000_symmetric_n20")
+    dq, rows, L = stored_rows.load_grad(cfg.name)
+    inp = synth.make_inputs(cfg, with_delta=False)
+    assert dq.shape == inp.qk.shape and len(rows) == 18 and L > 0
+    e = float((dq * inp.qk).sum()) / (6.0 * L) - 1.0
+    assert abs(e) <= 1e-11, e
