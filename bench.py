@@ -84,17 +84,28 @@ KERNEL_SOURCES = {"k_adj_fac": "k_adjoint_fac.hip", "k_triple_bt": "k_triple_mx.
                   "k_adj_fac64": "k_adjoint_fac64.hip", "k_triple_f64": "k_triple.hip"}
 
 
+def code_fingerprint(path: str) -> str:
+    """sha256[:16] of a source file's code: comments and white space removed,
+    so that an edit of comments alone keeps a measurement valid and any edit
+    of the code voids it."""
+    import hashlib
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256("".join(text.split()).encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel: str, tag: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
     summary profiles/<tag>_hbm_traffic.txt (FETCH_SIZE and WRITE_SIZE scaled
     by the copy-kernel calibration recorded there), or None when there is no
-    such record or the kernel's source has changed since it was measured."""
-    import hashlib
+    such record or the kernel's code has changed since it was measured."""
     path = os.path.join(ROOT, "profiles", f"{tag}_hbm_traffic.txt")
     if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
     src = os.path.join(ROOT, "paper_1503_08809_amd", "csrc", KERNEL_SOURCES[kernel])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = code_fingerprint(src)
     ff = wf = None
     for line in open(path):
         f = line.split()

@@ -40,8 +40,9 @@
 // accumulator are four apart), reading the next block's fragments while the
 // current one is multiplied; then generates its tiles of the next step from
 // the staged source rows (double-buffered in LDS, two rows per thread,
-// loaded three steps ahead); one barrier per step.  Against 32 rows x 16
-// shared pair tiles per wave this halves the LDS operand reads per step.
+// loaded three steps ahead); one barrier per step.  Sharing the generated
+// tiles through LDS instead (waves of 32 rows x all 16 tiles) would read
+// twice the operand bytes from LDS per step.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -227,7 +228,11 @@ __global__ __launch_bounds__(256, 2) void k_triple_bt(BTArgs A, const float *__r
         __builtin_amdgcn_s_barrier();
         sstore(P);                                                      // sources of step s + 2
         sload(s + 3 < last ? s + 3 : last);
-        acopy(s + 1 < last ? s + 1 : last, abn);                        // A of step s + 1
+        // A of step s + 1.  An LDS read that the compiler cannot tell apart
+        // from a copy's destination gets a wait for all copies in front of
+        // it; here the compiler issues this step's operand reads (buffer P)
+        // ahead of the copies (buffer 1 - P) and waits for none of them
+        acopy(s + 1 < last ? s + 1 : last, abn);
         // row block by row block, the next block's fragments read while this
         // one's 12 matrix-core operations run (product by product over the
         // four tiles, so that dependent operations are four apart)
