@@ -267,12 +267,21 @@ def test_gamma_lmax500_rows(mp, ctx):
 
 
 # ------------------------------------------------------------------ properties
-def test_deterministic(mp, ctx):
-    inp = _small(kind="symmetric")
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_deterministic(mp, ctx, prec):
+    """Run to run, bit for bit: no atomics and fixed summation orders in
+    every kernel, forward and adjoint (U = 289: several row blocks, tasks
+    and workgroups per CU)."""
+    inp = _small(kind="symmetric", n1=17, lmax=24, nr=5, nk=60)
     pr = mp.projection_from_inputs(ctx, inp)
-    a = _np(pr.gamma())
-    b = _np(pr.gamma())
+    a = _np(pr.gamma(prec))
+    b = _np(pr.gamma(prec))
     np.testing.assert_array_equal(a, b)
+    g = ctx.to_dev(np.cos(np.arange(a.size, dtype=np.float64)).reshape(a.shape))
+    dq1, dd1 = (_np(x) for x in pr.gamma_backward(g, prec))
+    dq2, dd2 = (_np(x) for x in pr.gamma_backward(g, prec))
+    np.testing.assert_array_equal(dq1, dq2)
+    np.testing.assert_array_equal(dd1, dd2)
 
 
 def test_host_pointers_match_device(mp, ctx):
