@@ -94,7 +94,6 @@ __global__ __launch_bounds__(256, 2) void k_triple_f64(TripleArgs A, const doubl
     const int2 tk = A.tasks[task];
     const int g = tk.x, rb = tk.y;
     const int t0 = A.group_tile0[g], nt = A.group_tile0[g + 1] - t0;
-    const int ngr = A.group_nrows[g];
     const int *grow = A.group_rows + (size_t)g * A.group_cap;
     const int row0 = rb * F64_ROWBLOCK;
 
