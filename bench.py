@@ -351,7 +351,7 @@ def main() -> int:
                     help="time the whole oracle on this host (small workloads), print, exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU r-sharding is a design, not built)", file=sys.stderr)
         return 2
     if args.ceilings:

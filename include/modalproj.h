@@ -71,7 +71,7 @@ typedef enum {
     MODAL_ERR_OOM = 3,           /* device allocation failed or over the cap   */
     MODAL_ERR_DEVICE = 4,        /* no usable device, or a HIP runtime error   */
     MODAL_ERR_NUMERIC = 5,       /* non-positive C_l, non-finite input         */
-    MODAL_ERR_UNSUPPORTED = 6    /* valid request this build does not handle   */
+    MODAL_ERR_UNSUPPORTED = 6    /* valid request the library does not handle  */
 } modal_status;
 
 /* Arithmetic of the projection.
