@@ -39,6 +39,14 @@ def normwise(a, ref):
     return float(np.abs(a - ref).max() / np.abs(ref).max())
 
 
+def large_rel(a, ref, frac=1e-3):
+    """Largest relative error over the entries of ref above frac of its
+    largest: an entry-wise check that a wrong subset of entries cannot hide
+    behind the largest ones."""
+    big = np.abs(ref) >= frac * np.abs(ref).max()
+    return float((np.abs(a - ref)[big] / np.abs(ref[big])).max())
+
+
 @pytest.mark.parametrize("kind,n1,lmax,nr,nk", [
     ("ordered", 3, 30, 7, 80),
     ("symmetric", 4, 30, 7, 80),
@@ -54,6 +62,7 @@ def test_backward_vs_oracle(mp, ctx, oracle, kind, n1, lmax, nr, nk):
     rq, rd = oracle.gamma_full_backward(inp, dG)
     assert normwise(_np(dq), rq) <= 1e-10
     assert normwise(_np(dd), rd) <= 1e-10
+    assert large_rel(_np(dq), rq) <= 1e-8 and large_rel(_np(dd), rd) <= 1e-8
 
 
 @pytest.mark.parametrize("kind,n1,lmax,nr,nk", [
@@ -72,8 +81,12 @@ def test_backward_mixed_vs_oracle(mp, ctx, oracle, kind, n1, lmax, nr, nk):
     dq, dd = pr.gamma_backward(ctx.to_dev(dG), "mixed")
     rq, rd = oracle.gamma_full_backward(inp, dG)
     eq, ed = normwise(_np(dq), rq), normwise(_np(dd), rd)
-    print(f"mixed adjoint {kind} n1={n1}: dq {eq:.2e}, ddelta {ed:.2e}")
+    # mixed: entries above 1e-2 of the largest (an entry far below it can be
+    # a deep cancellation, whose error follows the size of its terms)
+    lq, ld = large_rel(_np(dq), rq, 1e-2), large_rel(_np(dd), rd, 1e-2)
+    print(f"mixed adjoint {kind} n1={n1}: dq {eq:.2e}, ddelta {ed:.2e}; large entries {lq:.2e}, {ld:.2e}")
     assert eq <= 1e-4 and ed <= 1e-4
+    assert lq <= 1e-3 and ld <= 1e-3
 
 
 # U = n1^2 rows against the adjoint kernels' row blocks (FP64: 128 rows,
@@ -93,9 +106,11 @@ def test_backward_row_tails_vs_oracle(mp, ctx, oracle, prec, n1):
     dq, dd = pr.gamma_backward(ctx.to_dev(dG), prec)
     rq, rd = oracle.gamma_full_backward(inp, dG)
     eq, ed = normwise(_np(dq), rq), normwise(_np(dd), rd)
-    print(f"{prec} adjoint U={n1 * n1}: dq {eq:.2e}, ddelta {ed:.2e}")
-    tol = 1e-10 if prec == "fp64" else 1e-4
+    frac, tol, ltol = (1e-3, 1e-10, 1e-8) if prec == "fp64" else (1e-2, 1e-4, 1e-3)
+    lq, ld = large_rel(_np(dq), rq, frac), large_rel(_np(dd), rd, frac)
+    print(f"{prec} adjoint U={n1 * n1}: dq {eq:.2e}, ddelta {ed:.2e}; large entries {lq:.2e}, {ld:.2e}")
     assert eq <= tol and ed <= tol
+    assert lq <= ltol and ld <= ltol
 
 
 def test_backward_mixed_lmax500_vs_fp64(mp, ctx):
@@ -119,6 +134,7 @@ def test_backward_lmax64_vs_oracle(mp, ctx, oracle):
     rq, rd = oracle.gamma_full_backward(inp, dG)
     assert normwise(_np(dq), rq) <= 1e-10
     assert normwise(_np(dd), rd) <= 1e-10
+    assert large_rel(_np(dq), rq) <= 1e-8 and large_rel(_np(dd), rd) <= 1e-8
 
 
 def test_backward_host_outputs_and_null(mp, ctx):
