@@ -12,30 +12,50 @@
 // C_b[n m_total - n (n - 1) / 2 + (m - n)] (the upper triangle of C^T, which
 // is what Eq. (3D) keeps of its symmetric B_r).
 //
-// Workgroup: 256 threads, one T x T output tile (T = 64 or 128); each of the
-// four waves holds (T/2) x (T/2) in 16 x 16 matrix-core tiles.  K runs in
-// 16-deep tiles staged through LDS, two buffers: the next tile's loads are
-// issued before the current tile's matrix-core work and written to the other
-// buffer after it, one barrier per tile.  Loads outside the matrix are
-// clamped into it and zeroed only when written to LDS (no branch, so every
-// load of a tile stays in flight together).  Tiles are dealt to the 8 XCDs
-// in contiguous runs (M tile fastest), so the tiles that share a column
-// block of op(B) run on one XCD and read it through one L2.
+// Workgroup: one BT x BT output tile.  K runs in 16-deep steps whose
+// operands are copied from memory straight into LDS (buffer_load ... lds, no
+// registers) through a ring of slots, one array per slot, one barrier per
+// step; every LDS read is 16 bytes per lane and all of a step's reads are
+// issued before its copies.  BT = 64: four waves of 32 x 32, two slots
+// (copies one step ahead, 32 KB, four workgroups per CU); BT = 128: eight
+// waves of 64 (m) x 32 (n), three slots (copies two steps ahead, 96 KB, one
+// workgroup per CU).
+//
+// LDS layout of an operand in a slot, by how it lies in memory:
+//  * free index (m of op(A), n of op(B)) contiguous: rows [k][BT]; a lane
+//    reads two adjacent free indices, which feed the even and the odd one of
+//    a pair of 16-wide matrix-core tiles (tile 2p + e holds the free indices
+//    32 p + 2 r + e, r = 0..15);
+//  * k contiguous: [BT][k pair][2], the pair index XOR-swizzled by
+//    (free index / 2) mod 8 (a copy's 8 lanes of one free index read one
+//    128-byte run; the 16 free indices of a read fall in distinct banks); a
+//    lane reads the two k of one pair, which feed two consecutive
+//    matrix-core steps.
+// Inside a step the 16 k are taken in the order k = 2 (4 j + g) + e for
+// matrix-core step 2 j + e and lane group g (lane / 16), in both operands,
+// so that a 16-byte read serves either form.  Values outside the matrix are
+// read as zero (their buffer offset is out of range), except the second k of
+// a pair that straddles an odd K, which is zeroed in registers.
 //
 // FP64 16x16x4 operand layouts: A 16 x 4, lane l holds A[l % 16][l / 16];
 // B 4 x 16, lane l holds B[l / 16][l % 16]; result 16 x 16, lane l element
 // q holds D[4 q + l / 16][l % 16].  The product is formed as
-// op(B)^T op(A)^T = C^T, so that lane l holds C[m = l % 16][n = 4 q + l / 16]:
-// the 16 lanes of a group write 16 consecutive rows of one column of the
-// column-major C (128 bytes) instead of 4.
+// op(B)^T op(A)^T = C^T, so that a lane's results lie along m, the
+// contiguous index of the column-major C.
 #include "internal.hpp"
+
+#include <type_traits>
 
 namespace mp {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int TK = 16;
+constexpr int KS = 16;                         // k per step
+constexpr int kBufWord3 = 0x00020000;          // descriptor word 3: 32-bit data format, raw access
+constexpr uint32_t kOut = 0x80000000u;         // a buffer offset past every record: reads zero
+constexpr int kRecords = 0x7ffffff0;           // bytes a descriptor admits
 
 struct DgemmArgs {
     int m, n, k, batch;
@@ -47,6 +67,12 @@ struct DgemmArgs {
     double *C;
     int64_t ldc, sC;
 };
+
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t rs, uint32_t voff, void *lds_base)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)lds_base, 16, voff, 0,
+                                             0, 0);
+}
 
 // tile index (m tile, n tile, batch) of workgroup bid
 template <bool PACKED>
@@ -75,120 +101,221 @@ __device__ __forceinline__ void tile_of(int64_t bid, int mt, int nt, int64_t nti
     }
 }
 
-template <int T, bool TA, bool TB, bool PACKED>
-__global__ __launch_bounds__(256, 2) void k_dgemm(DgemmArgs g)
+// One operand's copies: instruction i (of BT / 8 per step) moves 1 KB, lane
+// `lane` 16 bytes.  Returns the lane's byte offset from the operand's step
+// origin (k = k0, free index = the tile's first); kk and f are the lane's
+// first k and free index inside the step.
+template <int BT>
+__device__ __forceinline__ uint32_t copy_offset(bool free, int i, int lane, int64_t ld, int &kk, int &f)
 {
-    constexpr int LD = T + 1;                 // padded LDS row (doubles)
-    constexpr int NL = T * TK / 256;          // values of each operand per thread and K tile
-    constexpr int WT = T / 32;                // 16 x 16 tiles per wave along m and n
-    __shared__ double As[2][TK][LD];
-    __shared__ double Bs[2][TK][LD];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int e = i * 128 + 2 * lane;                  // first value of the lane in the slot part
+    if (free) {
+        kk = e / BT;
+        f = e % BT;
+        return (uint32_t)(((int64_t)kk * ld + f) * 8);
+    }
+    // k contiguous: 16-byte position q = f * 8 + (pair ^ ((f >> 1) & 7)), so
+    // that the 8 lanes of one f read one 128-byte run and the 16 f a
+    // matrix-core read takes fall in 16 different bank groups
+    const int q = e / 2;
+    f = q / 8;
+    kk = 2 * ((q % 8) ^ ((f >> 1) & 7));
+    return (uint32_t)(((int64_t)f * ld + kk) * 8);
+}
+
+template <int BT, bool TA, bool TB, bool PACKED>
+__global__ __launch_bounds__(BT == 128 ? 512 : 256) __attribute__((amdgpu_waves_per_eu(BT == 128 ? 2 : 4))) void k_dgemm(DgemmArgs g)
+{
+    constexpr int NW = BT == 128 ? 8 : 4;          // waves
+    constexpr int WGN = NW / 2;                     // wave columns along n (two wave rows along m)
+    constexpr int WM = BT / 2, WN = BT / WGN;       // wave tile
+    constexpr int TMt = WM / 16, TNt = WN / 16;     // matrix-core tiles per wave along m and n
+    constexpr bool AF = !TA, BF = TB;               // free index contiguous in memory
+    constexpr int NI = BT / 8;                      // copies per operand and step (1 KB each)
+    constexpr int NDMA = 2 * NI / NW;               // copies per wave and step
+    constexpr int SLOT = 2 * KS * BT;               // doubles per slot: A part, then B part
+    constexpr int NSL = BT == 128 ? 3 : 2;          // ring slots (copies NSL - 1 steps ahead)
+    static_assert(TMt % 2 == 0 && TNt % 2 == 0 && NDMA * NW == 2 * NI && NDMA <= 15, "shape");
+    __shared__ d2 ring0[SLOT / 2], ring1[SLOT / 2], ring2[NSL == 3 ? SLOT / 2 : 1];
+
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = wave & 1, wn = wave >> 1;
     const int M = g.m, N = g.n, K = g.k;
-    const int mt = (M + T - 1) / T, nt = (N + T - 1) / T;
+    const int mt = (M + BT - 1) / BT, nt = (N + BT - 1) / BT;
     const int64_t ntiles = PACKED ? (int64_t)mt * (mt + 1) / 2 * g.batch : (int64_t)mt * nt * g.batch;
     const int64_t bid = blockIdx.x;
     if (bid >= ntiles) return;
     int tm, tn, b;
     tile_of<PACKED>(bid, mt, nt, ntiles, tm, tn, b);
-    const int m0 = tm * T, n0 = tn * T;
-    const double *A = g.A + (size_t)b * g.sA;
-    const double *B = g.B + (size_t)b * g.sB;
+    // uniform over the workgroup: kept in scalar registers
+    tm = __builtin_amdgcn_readfirstlane(tm);
+    tn = __builtin_amdgcn_readfirstlane(tn);
+    b = __builtin_amdgcn_readfirstlane(b);
+    const int m0 = tm * BT, n0 = tn * BT;
+    const double *Ab = g.A + (size_t)b * g.sA;
+    const double *Bb = g.B + (size_t)b * g.sB;
     double *C = g.C + (size_t)b * g.sC;
 
-    // staging map: NL values of A and NL of B per thread and K tile.  The
-    // loads only load (clamped into the matrix); which values lie outside
-    // it is kept as bits and applied when the tile is written to LDS, after
-    // the matrix-core work: a select on a loaded value at the load would
-    // make the compiler wait for each load in turn.
-    double ra[NL], rb[NL];
-    uint32_t okm = 0;                         // bit i: A value i inside, bit 16 + i: B value i
-    auto amap = [&](int i, int &m, int &kk) {
-        if (TA) { kk = t % TK; m = t / TK + 16 * i; }
-        else    { m = t % T;   kk = t / T + (256 / T) * i; }
-    };
-    auto bmap = [&](int i, int &n, int &k2) {
-        if (TB) { n = t % T;   k2 = t / T + (256 / T) * i; }
-        else    { k2 = t % TK; n = t / TK + 16 * i; }
-    };
-    auto load = [&](int k0) {
-        okm = 0;
+    // this wave's copies: instructions wave * NDMA .. + NDMA - 1 of the 2 NI,
+    // A's first, then B's, so that each wave copies from one operand only.
+    // Per copy: the lane's byte offset from the step origin (or an offset
+    // past every record where its free index lies outside the matrix) and
+    // its first k inside the step.
+    const bool wA = wave * NDMA < NI;
+    const int i0 = wA ? wave * NDMA : wave * NDMA - NI;
+    const bool fr = wA ? AF : BF;
+    const int64_t ld = wA ? g.lda : g.ldb;
+    const int f0 = wA ? m0 : n0, F = wA ? M : N;
+    uint32_t coff[NDMA];
+    int ck[NDMA];
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            int m, kk;
-            amap(i, m, kk);
-            const int gm = m0 + m, gk = k0 + kk;
-            const int cm = min(gm, M - 1), ck = min(gk, K - 1);
-            ra[i] = TA ? A[(size_t)cm * g.lda + ck] : A[(size_t)ck * g.lda + cm];
-            okm |= (uint32_t)(gm < M && gk < K) << i;
-            int n, k2;
-            bmap(i, n, k2);
-            const int gn = n0 + n, gk2 = k0 + k2;
-            const int cn = min(gn, N - 1), ck2 = min(gk2, K - 1);
-            rb[i] = TB ? B[(size_t)ck2 * g.ldb + cn] : B[(size_t)cn * g.ldb + ck2];
-            okm |= (uint32_t)(gn < N && gk2 < K) << (16 + i);
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            int m, kk;
-            amap(i, m, kk);
-            As[buf][kk][m] = (okm >> i) & 1 ? ra[i] : 0.0;
-            int n, k2;
-            bmap(i, n, k2);
-            Bs[buf][k2][n] = (okm >> (16 + i)) & 1 ? rb[i] : 0.0;
-        }
-    };
-
-    // acc[j][i]: the 16 x 16 tile (n block j, m block i) of C^T
-    d4 acc[WT][WT];
-#pragma unroll
-    for (int i = 0; i < WT; ++i)
-#pragma unroll
-        for (int j = 0; j < WT; ++j) acc[j][i] = d4{0.0, 0.0, 0.0, 0.0};
-
-    const int ktiles = (K + TK - 1) / TK;
-    if (ktiles > 0) {
-        load(0);
-        stash(0);
+    for (int c = 0; c < NDMA; ++c) {
+        int kk, f;
+        const uint32_t o = copy_offset<BT>(fr, i0 + c, lane, ld, kk, f);
+        coff[c] = f0 + f < F ? o : kOut;
+        ck[c] = kk;
     }
-    __syncthreads();
-    for (int kt = 0; kt < ktiles; ++kt) {
-        const int buf = kt & 1;
-        const bool more = kt + 1 < ktiles;
-        if (more) load((kt + 1) * TK);
+    const int nsteps = (K + KS - 1) / KS;
+    // the operand's origin at step s is base0 + 16 s kst elements from its
+    // matrix, whose last element is ext - 1
+    const double *P = wA ? Ab : Bb;
+    const int64_t ext = wA ? (TA ? (int64_t)(M - 1) * g.lda + K : (int64_t)(K - 1) * g.lda + M)
+                           : (TB ? (int64_t)(K - 1) * g.ldb + N : (int64_t)(N - 1) * g.ldb + K);
+    const int64_t base0 = fr ? f0 : (int64_t)f0 * ld;
+    const int64_t kst = fr ? ld : 1;
+    const int dpart = (wA ? 0 : KS * BT) + i0 * 128;       // doubles into the slot
+    auto issue = [&](int s, d2 *r) {
+        const int k0 = min(s, nsteps - 1) * KS;
+        const int64_t org = base0 + (int64_t)k0 * kst;
+        // the descriptor admits the operand's bytes from the step origin to
+        // its last element, so that no copy reads outside the matrix
+        const int64_t bytes = (ext - org) * 8;
+        const int rec = bytes < kRecords ? (int)bytes : kRecords;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)(P + org), 0, rec, kBufWord3);
+        double *d = reinterpret_cast<double *>(r) + dpart;
+        if (k0 + KS <= K) {
 #pragma unroll
-        for (int ks = 0; ks < TK / 4; ++ks) {
-            const int kr = ks * 4 + (lane >> 4);
-            double av[WT], bv[WT];
+            for (int c = 0; c < NDMA; ++c) dma16(rs, coff[c], d + c * 128);
+        } else {
 #pragma unroll
-            for (int i = 0; i < WT; ++i) av[i] = As[buf][kr][wm * (T / 2) + i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < WT; ++j) bv[j] = Bs[buf][kr][wn * (T / 2) + j * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < WT; ++j)
-#pragma unroll
-                for (int i = 0; i < WT; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[j], av[i], acc[j][i], 0, 0, 0);
+            for (int c = 0; c < NDMA; ++c) dma16(rs, k0 + ck[c] < K ? coff[c] : kOut, d + c * 128);
         }
-        // the other buffer was last read in tile kt - 1, before the barrier
-        // that ended it
-        if (more) stash(buf ^ 1);
-        __syncthreads();
-    }
+    };
 
+    // 16-byte position of (free index f, k pair p) in the k-contiguous form
+    auto kpos = [](int f, int p) { return f * 8 + (p ^ ((f >> 1) & 7)); };
+    // operand reads of a step: lane (r = lane % 16, group gg = lane / 16)
+    const int r16 = lane & 15, gg = lane >> 4;
+    d4 acc[TNt][TMt];
+#pragma unroll
+    for (int j = 0; j < TNt; ++j)
+#pragma unroll
+        for (int i = 0; i < TMt; ++i) acc[j][i] = d4{0.0, 0.0, 0.0, 0.0};
+
+    int s = 0;
+    auto step = [&](auto slot) -> bool {
+        constexpr int S = decltype(slot)::value;
+        const d2 *const rg = S == 0 ? ring0 : (S == 1 ? ring1 : ring2);
+        d2 *const rn = NSL == 2 ? (S == 0 ? ring1 : ring0) : (S == 0 ? ring2 : (S == 1 ? ring0 : ring1));
+        // this wave's copies of step s are done once at most the next step's
+        // NDMA are outstanding (with two slots: none)
+        __builtin_amdgcn_s_waitcnt(0x0f70 | (NSL == 3 ? NDMA : 0));     // vmcnt(NDMA) or vmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        const double *ra = reinterpret_cast<const double *>(rg);
+        const double *rb = ra + KS * BT;
+        // a[j][x][e2]: m side; b[j][y][e2]: n side.  For the free form x (y)
+        // runs over tile pairs and e2 over the pair's even / odd tile at k
+        // step 2 j + e; for the k form x (y) runs over tiles and e2 over the
+        // two k steps 2 j, 2 j + 1.
+        d2 a[2][2][TMt], bv[2][2][TNt];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (AF) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+#pragma unroll
+                    for (int p = 0; p < TMt / 2; ++p)
+                        a[j][e][p] = *reinterpret_cast<const d2 *>(ra + (2 * (4 * j + gg) + e) * BT + wm * WM + 32 * p +
+                                                                   2 * r16);
+            } else {
+#pragma unroll
+                for (int i = 0; i < TMt; ++i)
+                    a[j][0][i] = *reinterpret_cast<const d2 *>(ra + kpos(wm * WM + 16 * i + r16, 4 * j + gg) * 2);
+            }
+            if (BF) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+#pragma unroll
+                    for (int p = 0; p < TNt / 2; ++p)
+                        bv[j][e][p] = *reinterpret_cast<const d2 *>(rb + (2 * (4 * j + gg) + e) * BT + wn * WN + 32 * p +
+                                                                    2 * r16);
+            } else {
+#pragma unroll
+                for (int i = 0; i < TNt; ++i)
+                    bv[j][0][i] = *reinterpret_cast<const d2 *>(rb + kpos(wn * WN + 16 * i + r16, 4 * j + gg) * 2);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        issue(s + NSL - 1, rn);
+        __builtin_amdgcn_sched_barrier(0);
+        // the second k of a pair straddling an odd K lies outside the matrix
+        const int k0 = s * KS;
+        if (k0 + KS > K) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bool out = k0 + 2 * (4 * j + gg) + 1 >= K;
+                if (!AF)
+#pragma unroll
+                    for (int i = 0; i < TMt; ++i) a[j][0][i].y = out ? 0.0 : a[j][0][i].y;
+                if (!BF)
+#pragma unroll
+                    for (int i = 0; i < TNt; ++i) bv[j][0][i].y = out ? 0.0 : bv[j][0][i].y;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int y = 0; y < TNt; ++y)
+#pragma unroll
+                    for (int x = 0; x < TMt; ++x) {
+                        const double av = AF ? a[j][e][x >> 1][x & 1] : a[j][0][x][e];
+                        const double bw = BF ? bv[j][e][y >> 1][y & 1] : bv[j][0][y][e];
+                        acc[y][x] = __builtin_amdgcn_mfma_f64_16x16x4f64(bw, av, acc[y][x], 0, 0, 0);
+                    }
+        return ++s < nsteps;
+    };
+    if (nsteps > 0) {
+        issue(0, ring0);
+        if (NSL == 3) issue(1, ring1);
+        for (;;) {
+            if (!step(std::integral_constant<int, 0>())) break;
+            if (!step(std::integral_constant<int, 1>())) break;
+            if constexpr (NSL == 3)
+                if (!step(std::integral_constant<int, 2>())) break;
+        }
+    }
+    // no copy into this workgroup's LDS may outlive it
+    __builtin_amdgcn_s_waitcnt(0x0f70);                                 // vmcnt(0)
+
+    // lane l element q of tile (y, x): n side row 4 q + gg, m side column r16
+    auto mof = [&](int x) { return m0 + wm * WM + (AF ? 32 * (x >> 1) + 2 * r16 + (x & 1) : 16 * x + r16); };
+    auto nof = [&](int y, int q) {
+        const int rr = 4 * q + gg;
+        return n0 + wn * WN + (BF ? 32 * (y >> 1) + 2 * rr + (y & 1) : 16 * y + rr);
+    };
     const double alpha = g.alpha, beta = g.beta;
 #pragma unroll
-    for (int j = 0; j < WT; ++j)
+    for (int y = 0; y < TNt; ++y)
 #pragma unroll
-        for (int i = 0; i < WT; ++i)
+        for (int q = 0; q < 4; ++q) {
+            const int n = nof(y, q);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int m = m0 + wm * (T / 2) + i * 16 + (lane & 15);
-                const int n = n0 + wn * (T / 2) + j * 16 + 4 * q + (lane >> 4);
-                const double v = alpha * acc[j][i][q];
+            for (int x = 0; x < TMt; ++x) {
+                const int m = mof(x);
+                const double v = alpha * acc[y][x][q];
                 if (!PACKED) {
                     if (m < M && n < N) {
                         double *p = C + (size_t)n * g.ldc + m;
@@ -198,16 +325,17 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(DgemmArgs g)
                     C[(int64_t)n * M - (int64_t)n * (n - 1) / 2 + (m - n)] = v;
                 }
             }
+        }
 }
 
-template <int T, bool PACKED>
+template <int BT, bool PACKED>
 hipError_t launch_t(bool ta, bool tb, const DgemmArgs &g, int64_t tiles, hipStream_t s)
 {
-    const dim3 grid((unsigned)tiles), block(256);
-    if (!ta && !tb)     hipLaunchKernelGGL((k_dgemm<T, false, false, PACKED>), grid, block, 0, s, g);
-    else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<T, true, false, PACKED>), grid, block, 0, s, g);
-    else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<T, false, true, PACKED>), grid, block, 0, s, g);
-    else                hipLaunchKernelGGL((k_dgemm<T, true, true, PACKED>), grid, block, 0, s, g);
+    const dim3 grid((unsigned)tiles), block(BT == 128 ? 512 : 256);
+    if (!ta && !tb)     hipLaunchKernelGGL((k_dgemm<BT, false, false, PACKED>), grid, block, 0, s, g);
+    else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<BT, true, false, PACKED>), grid, block, 0, s, g);
+    else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<BT, false, true, PACKED>), grid, block, 0, s, g);
+    else                hipLaunchKernelGGL((k_dgemm<BT, true, true, PACKED>), grid, block, 0, s, g);
     return hipGetLastError();
 }
 
