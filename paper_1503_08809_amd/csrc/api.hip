@@ -1446,7 +1446,7 @@ modal_status modal_gamma_3d(modal_ctx c, const modal_grid *g, const modal_proble
         need(c, gamma != nullptr, MODAL_ERR_INVALID_ARG, "gamma must be non-NULL");
         Dims d = check_grid(c, g, false);
         check_problem(c, p, d, true, true);
-        need(c, d.U <= 1280, MODAL_ERR_SHAPE, "np * na above 1280: the moment tensor (8 (np na)^3 bytes) is too large");
+        need(c, d.U <= 1280, MODAL_ERR_SHAPE, "np * na above 1280: the moment tensor (about 4 (np na)^3 bytes) is too large");
         OutBuf o = dev_out(c, gamma, (size_t)p->ta * p->tp, W_GAMMA);
         run_gamma_3d(c, g, p, d, threej, o.dev);
         finish_out(c, o);

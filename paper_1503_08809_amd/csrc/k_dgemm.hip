@@ -56,6 +56,9 @@ constexpr int KS = 16;                         // k per step
 constexpr int kBufWord3 = 0x00020000;          // descriptor word 3: 32-bit data format, raw access
 constexpr uint32_t kOut = 0x80000000u;         // a buffer offset past every record: reads zero
 constexpr int kRecords = 0x7ffffff0;           // bytes a descriptor admits
+// leading dimensions up to this keep every copy's byte offset inside one
+// step below kRecords (128 rows of the k-contiguous form)
+constexpr int64_t kMaxLd = kRecords / (8 * 128) - 1;
 
 struct DgemmArgs {
     int m, n, k, batch;
@@ -348,6 +351,7 @@ hipError_t launch_dgemm(bool ta, bool tb, int m, int n, int k, double alpha, con
     if (m < 0 || n < 0 || k < 0 || batch < 0 || (tile != 64 && tile != 128)) return hipErrorInvalidValue;
     if (m == 0 || n == 0 || batch == 0) return hipSuccess;
     if (ldc < m || lda < (ta ? k : m) || ldb < (tb ? n : k)) return hipErrorInvalidValue;
+    if (lda > kMaxLd || ldb > kMaxLd) return hipErrorInvalidValue;
     const int64_t tiles = (int64_t)((m + tile - 1) / tile) * ((n + tile - 1) / tile) * batch;
     if (tiles > INT32_MAX) return hipErrorInvalidValue;
     DgemmArgs g{m, n, k, batch, alpha, beta, A, lda, sA, B, ldb, sB, C, ldc, sC};
@@ -362,6 +366,7 @@ hipError_t launch_dgemm_packed_lower(bool ta, bool tb, int m, int k, const doubl
     if (m < 0 || k < 0 || batch < 0) return hipErrorInvalidValue;
     if (m == 0 || batch == 0) return hipSuccess;
     if (lda < (ta ? k : m) || ldb < (tb ? m : k) || sP < (int64_t)m * (m + 1) / 2) return hipErrorInvalidValue;
+    if (lda > kMaxLd || ldb > kMaxLd) return hipErrorInvalidValue;
     const int64_t mt = (m + T - 1) / T;
     const int64_t tiles = mt * (mt + 1) / 2 * batch;
     if (tiles > INT32_MAX) return hipErrorInvalidValue;
