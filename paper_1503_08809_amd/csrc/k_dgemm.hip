@@ -127,7 +127,8 @@ __device__ __forceinline__ uint32_t copy_offset(bool free, int i, int lane, int6
 }
 
 template <int BT, bool TA, bool TB, bool PACKED>
-__global__ __launch_bounds__(BT == 128 ? 512 : 256) __attribute__((amdgpu_waves_per_eu(BT == 128 ? 2 : 4))) void k_dgemm(DgemmArgs g)
+__global__ __launch_bounds__(BT == 128 ? 512 : 256)
+__attribute__((amdgpu_waves_per_eu(BT == 128 ? 2 : 4))) void k_dgemm(DgemmArgs g)
 {
     constexpr int NW = BT == 128 ? 8 : 4;          // waves
     constexpr int WGN = NW / 2;                     // wave columns along n (two wave rows along m)
