@@ -135,10 +135,13 @@ def test_3d_workspace_limit_too_small(mp, ctx):
         c2.close()
 
 
-@pytest.mark.parametrize("kind,n1,lmax,nr", [("symmetric", 4, 300, 6), ("ordered", 3, 517, 5)])
+@pytest.mark.parametrize("kind,n1,lmax,nr", [("symmetric", 4, 300, 6), ("ordered", 3, 517, 5),
+                                             ("symmetric", 9, 302, 4)])
 def test_3d_vs_separable(mp, ctx, kind, n1, lmax, nr):
     """Several 128-row chunks of the l3 band and an odd lmax: Eq. (3D) (exact
-    symbol) against Eq. (2D) on the GPU."""
+    symbol) against Eq. (2D) on the GPU.  The last case has 81 modes (two
+    64-wide product tiles, the second ragged) and 301 l values (an odd depth
+    in the per-r products over l)."""
     inp = synth.make_inputs(synth.small_config(lmax=lmax, nk=300, nr=nr, n1=n1, kind=kind, seed_index=98))
     pr = mp.projection_from_inputs(ctx, inp)
     err = normwise(_np(pr.gamma_3d("exact")), _np(pr.gamma("fp64")))
